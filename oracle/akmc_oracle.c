@@ -1,0 +1,489 @@
+/*
+ * akmc_oracle.c -- plain, slow CPU reference of the classical AKMC
+ * vacancy-jump path (rates, selection, time, swap) for BCC alloys.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  The HIP library never
+ * calls it, links it or shares a line of code, a header or a table with it.
+ *
+ * What is computed, following the paper:
+ *   - Classical AKMC (Sec. III-B1): before every event, every migration
+ *     direction of every vacancy is enumerated and its rate evaluated.
+ *     This oracle does exactly that: a full recompute of all rates at every
+ *     event, with no incremental bookkeeping.
+ *   - Rate of a candidate: the Arrhenius law of Eq. 8, r = nu exp(-Ea/kB T).
+ *   - Feasibility mask (Eq. 1): a jump whose target site holds a vacancy is
+ *     inadmissible and gets rate zero.
+ *   - Selection: one event out of all candidates of the whole system, with
+ *     probability proportional to its rate (the system-wide competition of
+ *     Eq. 2, here with logits ln r).
+ *   - Physical time: the increment is inversely proportional to the total
+ *     rate (Sec. II); its mean 1/Gamma_tot follows from the first-passage
+ *     relation of Eq. 5.
+ * The paper does not state the energy model, the lattice, the random
+ * stream or the summation order.  The readings used here are:
+ *   - BCC, lx*ly*lz cubic cells, periodic, 2 sites per cell, each edge >= 3.
+ *     Site index = b*lx*ly*lz + (z*ly + y)*lx + x, b = 0 cube corner,
+ *     b = 1 body centre.
+ *   - 1NN direction k = 4*[sx>0] + 2*[sy>0] + [sz>0] for the half-diagonal
+ *     displacement (sx, sy, sz)*a/2; 2NN index m walks (+x,-x,+y,-y,+z,-z).
+ *   - Energy: sum over 1NN and 2NN bonds of symmetric pair energies
+ *     eps1[a][b], eps2[a][b], vacancy rows included.
+ *   - Energy change of the jump "vacancy at i <- atom A at j" from the bonds
+ *     it changes, as integer species counts times
+ *     D_k[A][s] = eps_k[A][s] - eps_k[V][s], accumulated as one
+ *     fused-multiply-add chain over s, shell 1 first.
+ *   - Kang-Weinberg barrier Ea = E0[A] + dE/2 (no clamp).
+ *   - Random stream: Philox4x64-10 (Salmon et al., SC'11), key
+ *     (seed, stream_id), counter (n, 0, 0, 0) for global event index n;
+ *     u1 = (x0 >> 11) 2^-53, u2 = ((x1 >> 11) + 1) 2^-53.
+ *   - Selection: candidates c = 8*slot + k in slot order, slots ordered by
+ *     ascending site at creation and following their vacancy; the chosen
+ *     c is the first whose running sum exceeds u1*Gamma_tot (plain
+ *     left-to-right sums), falling back to the last positive rate.
+ *   - dt = -ln(u2)/Gamma_tot (or 1/Gamma_tot in mean-time mode).
+ *   - Event digest: FNV-1a 64 over the little-endian bytes of
+ *     (n:int64, from:int32, to:int32) per event.
+ *
+ * Precision: fp64 throughout by default.  A second mode computes energy
+ * change, barrier and rate in binary32 (fmaf chain, binary32 division,
+ * expf) and widens the rate to binary64 before any sum; it exists so that
+ * the oracle takes selection decisions in the same precision as a binary32
+ * rate kernel.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    int32_t lx, ly, lz;
+    int32_t n_species;           /* S; the vacancy code is S-1 */
+    double eps1[64];             /* S*S row-major, eV */
+    double eps2[64];
+    double e0[8];                /* per migrating species, eV */
+    double nu;                   /* Hz */
+    double temperature;          /* K */
+    double kb;                   /* eV/K */
+    uint64_t seed;
+    uint64_t stream_id;
+    int32_t precision;           /* 0 = binary64, 1 = binary32 energies/rates */
+    int32_t time_mode;           /* 0 = -ln(u2)/G, 1 = 1/G */
+} orc_params;
+
+typedef struct {
+    int64_t n;                   /* global event index */
+    int32_t slot;
+    int32_t from_site;           /* vacancy site before the jump */
+    int32_t to_site;             /* vacancy site after the jump */
+    uint8_t dir;
+    uint8_t species;             /* species of the atom that moved */
+    uint8_t pad[2];
+    double gamma_tot;            /* total rate of the state before the jump */
+    double dt;
+} orc_event;
+
+typedef struct {
+    int64_t n;                   /* next global event index */
+    double t;                    /* physical time, s */
+    uint64_t digest;
+    double gamma_tot;            /* total rate of the current state */
+    int64_t n_neg_barrier;       /* evaluated candidates with Ea < 0 */
+} orc_state;
+
+/* ---------------------------------------------------------------- lattice */
+
+static int64_t n_cells(const orc_params *p) {
+    return (int64_t)p->lx * p->ly * p->lz;
+}
+
+static int wrap(int a, int L) {
+    int r = a % L;
+    return r < 0 ? r + L : r;
+}
+
+int32_t orc_site(const orc_params *p, int b, int x, int y, int z) {
+    x = wrap(x, p->lx);
+    y = wrap(y, p->ly);
+    z = wrap(z, p->lz);
+    return (int32_t)(b * n_cells(p) + ((int64_t)z * p->ly + y) * p->lx + x);
+}
+
+void orc_decode(const orc_params *p, int32_t s, int *b, int *x, int *y, int *z) {
+    int64_t nc = n_cells(p);
+    *b = (int)(s / nc);
+    int64_t r = s % nc;
+    *x = (int)(r % p->lx);
+    r /= p->lx;
+    *y = (int)(r % p->ly);
+    *z = (int)(r / p->ly);
+}
+
+int32_t orc_nbr1(const orc_params *p, int32_t s, int k) {
+    int b, x, y, z;
+    orc_decode(p, s, &b, &x, &y, &z);
+    int px = (k >> 2) & 1, py = (k >> 1) & 1, pz = k & 1;
+    if (b == 0) /* corner: +1/2 lands in this cell's centre, -1/2 in the previous cell's */
+        return orc_site(p, 1, x - !px, y - !py, z - !pz);
+    /* centre: +1/2 lands on the next cell's corner, -1/2 on this cell's */
+    return orc_site(p, 0, x + px, y + py, z + pz);
+}
+
+int32_t orc_nbr2(const orc_params *p, int32_t s, int m) {
+    int b, x, y, z;
+    orc_decode(p, s, &b, &x, &y, &z);
+    int step = (m & 1) ? -1 : 1;
+    int axis = m >> 1;
+    if (axis == 0) x += step;
+    else if (axis == 1) y += step;
+    else z += step;
+    return orc_site(p, b, x, y, z);
+}
+
+/* --------------------------------------------------------------- energies */
+
+static double dtab(const double *eps, int S, int a, int s) {
+    int v = S - 1;
+    return eps[a * S + s] - eps[v * S + s];
+}
+
+/* Species-count differences of the bonds the jump changes.  The vacancy
+ * sits at i (whatever occ[i] holds), the atom at j = nbr1(i, k) moves to i.
+ *   dn1[s] = #{n in N1(i)\{j}: s} - #{n in N1(j)\{i}: s}
+ *   dn2[s] = #{n in N2(i):     s} - #{n in N2(j):     s}            */
+static int counts(const orc_params *p, const uint8_t *occ, int32_t i, int k,
+                  int dn1[8], int dn2[8]) {
+    int32_t j = orc_nbr1(p, i, k);
+    for (int s = 0; s < 8; s++) { dn1[s] = 0; dn2[s] = 0; }
+    for (int q = 0; q < 8; q++) {
+        int32_t n = orc_nbr1(p, i, q);
+        if (n != j) dn1[occ[n]] += 1;
+    }
+    for (int q = 0; q < 8; q++) {
+        int32_t n = orc_nbr1(p, j, q);
+        if (n != i) dn1[occ[n]] -= 1;
+    }
+    for (int m = 0; m < 6; m++) dn2[occ[orc_nbr2(p, i, m)]] += 1;
+    for (int m = 0; m < 6; m++) dn2[occ[orc_nbr2(p, j, m)]] -= 1;
+    return occ[j];
+}
+
+/* Energy change of the jump, binary64.  Returns NaN for a masked jump. */
+double orc_delta_e(const orc_params *p, const uint8_t *occ, int32_t i, int k) {
+    int S = p->n_species, dn1[8], dn2[8];
+    int A = counts(p, occ, i, k, dn1, dn2);
+    if (A == S - 1) return NAN;
+    double acc = 0.0;
+    for (int s = 0; s < S; s++) acc = fma((double)dn1[s], dtab(p->eps1, S, A, s), acc);
+    for (int s = 0; s < S; s++) acc = fma((double)dn2[s], dtab(p->eps2, S, A, s), acc);
+    return acc;
+}
+
+/* Barrier and rate of one candidate.  Masked: Ea = +inf, rate = +0. */
+void orc_candidate(const orc_params *p, const uint8_t *occ, int32_t i, int k,
+                   double *ea_out, double *rate_out) {
+    int S = p->n_species, dn1[8], dn2[8];
+    int A = counts(p, occ, i, k, dn1, dn2);
+    if (A == S - 1) {
+        *ea_out = INFINITY;
+        *rate_out = 0.0;
+        return;
+    }
+    if (p->precision == 0) {
+        double acc = 0.0;
+        for (int s = 0; s < S; s++) acc = fma((double)dn1[s], dtab(p->eps1, S, A, s), acc);
+        for (int s = 0; s < S; s++) acc = fma((double)dn2[s], dtab(p->eps2, S, A, s), acc);
+        double ea = p->e0[A] + 0.5 * acc;
+        double kt = p->kb * p->temperature;
+        double x = -(ea / kt);
+        *ea_out = ea;
+        *rate_out = p->nu * exp(x);
+    } else {
+        float acc = 0.0f;
+        for (int s = 0; s < S; s++) acc = fmaf((float)dn1[s], (float)dtab(p->eps1, S, A, s), acc);
+        for (int s = 0; s < S; s++) acc = fmaf((float)dn2[s], (float)dtab(p->eps2, S, A, s), acc);
+        float ea = (float)p->e0[A] + 0.5f * acc;
+        float kt = (float)(p->kb * p->temperature);
+        float x = -(ea / kt);
+        float r = (float)p->nu * expf(x);
+        *ea_out = (double)ea;
+        *rate_out = (double)r;
+    }
+}
+
+/* rates[n][8], ea[n][8] for a vacancy placed at each listed site. */
+void orc_rates_sites(const orc_params *p, const uint8_t *occ, const int32_t *sites,
+                     int64_t n, double *rates, double *ea) {
+    for (int64_t a = 0; a < n; a++)
+        for (int k = 0; k < 8; k++) {
+            double e, r;
+            orc_candidate(p, occ, sites[a], k, &e, &r);
+            rates[a * 8 + k] = r;
+            if (ea) ea[a * 8 + k] = e;
+        }
+}
+
+/* ------------------------------------------------------------------ Philox */
+
+static uint64_t mulhilo64(uint64_t a, uint64_t b, uint64_t *hi) {
+    __uint128_t prod = (__uint128_t)a * (__uint128_t)b;
+    *hi = (uint64_t)(prod >> 64);
+    return (uint64_t)prod;
+}
+
+/* Philox4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11). */
+void orc_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4]) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+    uint64_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; r++) {
+        uint64_t hi0, hi1;
+        uint64_t lo0 = mulhilo64(M0, x0, &hi0);
+        uint64_t lo1 = mulhilo64(M1, x2, &hi1);
+        uint64_t y0 = hi1 ^ x1 ^ k0, y1 = lo1, y2 = hi0 ^ x3 ^ k1, y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+void orc_uniforms(uint64_t seed, uint64_t stream_id, int64_t n, double *u1, double *u2) {
+    uint64_t ctr[4] = {(uint64_t)n, 0, 0, 0}, key[2] = {seed, stream_id}, x[4];
+    orc_philox4x64_10(ctr, key, x);
+    const double two_m53 = 1.0 / 9007199254740992.0;
+    *u1 = (double)(x[0] >> 11) * two_m53;
+    *u2 = (double)((x[1] >> 11) + 1) * two_m53;
+}
+
+/* ---------------------------------------------------------------- digest */
+
+uint64_t orc_fnv1a(uint64_t h, const uint8_t *bytes, int64_t n) {
+    for (int64_t a = 0; a < n; a++) {
+        h ^= bytes[a];
+        h *= 0x100000001b3ULL;
+    }
+    return h;
+}
+
+static uint64_t digest_event(uint64_t h, int64_t n, int32_t from, int32_t to) {
+    uint8_t b[16];
+    for (int a = 0; a < 8; a++) b[a] = (uint8_t)((uint64_t)n >> (8 * a));
+    for (int a = 0; a < 4; a++) b[8 + a] = (uint8_t)((uint32_t)from >> (8 * a));
+    for (int a = 0; a < 4; a++) b[12 + a] = (uint8_t)((uint32_t)to >> (8 * a));
+    return orc_fnv1a(h, b, 16);
+}
+
+/* -------------------------------------------------------------- selection */
+
+/* First candidate whose left-to-right running sum exceeds u1*Gamma_tot;
+ * falls back to the last positive rate.  Returns -1 when Gamma_tot is not
+ * positive (frozen state). */
+int64_t orc_select(const double *rates, int64_t n, double u1, double *gamma_tot) {
+    double g = 0.0;
+    for (int64_t c = 0; c < n; c++) g += rates[c];
+    if (gamma_tot) *gamma_tot = g;
+    if (!(g > 0.0)) return -1;
+    double target = u1 * g, run = 0.0;
+    int64_t last = -1;
+    for (int64_t c = 0; c < n; c++) {
+        run += rates[c];
+        if (rates[c] > 0.0) last = c;
+        if (run > target) return c;
+    }
+    return last;
+}
+
+static void all_rates(const orc_params *p, const uint8_t *occ, const int32_t *slots,
+                      int32_t nv, double *rates, int64_t *n_neg) {
+    for (int32_t v = 0; v < nv; v++)
+        for (int k = 0; k < 8; k++) {
+            double e, r;
+            orc_candidate(p, occ, slots[v], k, &e, &r);
+            rates[v * 8 + k] = r;
+            if (n_neg && e < 0.0) *n_neg += 1;
+        }
+}
+
+/* Total rate of the current state (plain sum of all candidates). */
+double orc_gamma_tot(const orc_params *p, const uint8_t *occ, const int32_t *slots,
+                     int32_t nv) {
+    double *rates = (double *)malloc(sizeof(double) * 8 * (size_t)(nv > 0 ? nv : 1));
+    all_rates(p, occ, slots, nv, rates, NULL);
+    double g = 0.0;
+    for (int64_t c = 0; c < 8 * (int64_t)nv; c++) g += rates[c];
+    free(rates);
+    return g;
+}
+
+/* Runs n_events events from (occ, slots, st).  Returns the number of events
+ * done; -4 if the state is frozen before any event could be done (then
+ * nothing changes).  log may be NULL. */
+int64_t orc_run(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
+                orc_state *st, int64_t n_events, orc_event *events) {
+    int V = p->n_species - 1;
+    double *rates = (double *)malloc(sizeof(double) * 8 * (size_t)(nv > 0 ? nv : 1));
+    int64_t done = 0;
+    for (int64_t e = 0; e < n_events; e++) {
+        all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
+        double u1, u2, g;
+        orc_uniforms(p->seed, p->stream_id, st->n, &u1, &u2);
+        int64_t c = orc_select(rates, 8 * (int64_t)nv, u1, &g);
+        if (c < 0) {
+            st->gamma_tot = g;
+            free(rates);
+            return done > 0 ? done : -4;
+        }
+        int32_t v = (int32_t)(c / 8);
+        int k = (int)(c % 8);
+        int32_t i = slots[v], j = orc_nbr1(p, i, k);
+        double dt = (p->time_mode == 1) ? 1.0 / g : -log(u2) / g;
+        if (events) {
+            orc_event *ev = &events[e];
+            memset(ev, 0, sizeof(*ev));
+            ev->n = st->n;
+            ev->slot = v;
+            ev->from_site = i;
+            ev->to_site = j;
+            ev->dir = (uint8_t)k;
+            ev->species = occ[j];
+            ev->gamma_tot = g;
+            ev->dt = dt;
+        }
+        occ[i] = occ[j];
+        occ[j] = (uint8_t)V;
+        slots[v] = j;
+        st->digest = digest_event(st->digest, st->n, i, j);
+        st->t += dt;
+        st->n += 1;
+        done += 1;
+    }
+    st->gamma_tot = orc_gamma_tot(p, occ, slots, nv);
+    free(rates);
+    return done;
+}
+
+/* Replays a given event log on (occ, slots, st) in binary64 and reports how
+ * well every recorded choice agrees with the binary64 rates of the state it
+ * was taken from:
+ *   out[0] = max over events of the selection-interval violation, relative
+ *            to Gamma_tot: max(0, C_{c-1} - u1 G, u1 G - C_c) / G
+ *   out[1] = max relative difference of the recorded Gamma_tot
+ *   out[2] = max relative difference of the recorded dt
+ *   out[3] = number of structural mismatches (wrong index, site, species,
+ *            a masked candidate chosen)
+ * The swaps recorded in the log are applied, so occ/slots end where the
+ * logged trajectory ends. */
+void orc_follow(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
+                orc_state *st, int64_t n_events, const orc_event *events, double out[4]) {
+    int V = p->n_species - 1;
+    double *rates = (double *)malloc(sizeof(double) * 8 * (size_t)(nv > 0 ? nv : 1));
+    out[0] = out[1] = out[2] = out[3] = 0.0;
+    for (int64_t e = 0; e < n_events; e++) {
+        const orc_event *ev = &events[e];
+        all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
+        double u1, u2;
+        orc_uniforms(p->seed, p->stream_id, st->n, &u1, &u2);
+        double g = 0.0;
+        for (int64_t c = 0; c < 8 * (int64_t)nv; c++) g += rates[c];
+        int64_t c = (int64_t)ev->slot * 8 + ev->dir;
+        int bad = 0;
+        if (ev->n != st->n || ev->slot < 0 || ev->slot >= nv || ev->dir > 7) bad = 1;
+        if (!bad) {
+            double before = 0.0;
+            for (int64_t q = 0; q < c; q++) before += rates[q];
+            double after = before + rates[c];
+            double target = u1 * g;
+            double viol = 0.0;
+            if (before - target > viol) viol = before - target;
+            if (target - after > viol) viol = target - after;
+            if (viol / g > out[0]) out[0] = viol / g;
+            if (!(rates[c] > 0.0)) bad = 1;
+            double dg = fabs(ev->gamma_tot - g) / g;
+            if (dg > out[1]) out[1] = dg;
+            double dt = (p->time_mode == 1) ? 1.0 / g : -log(u2) / g;
+            double ddt = fabs(ev->dt - dt) / dt;
+            if (ddt > out[2]) out[2] = ddt;
+            int32_t i = slots[ev->slot], j = orc_nbr1(p, i, ev->dir);
+            if (ev->from_site != i || ev->to_site != j || ev->species != occ[j]) bad = 1;
+            if (!bad) {
+                occ[i] = occ[j];
+                occ[j] = (uint8_t)V;
+                slots[ev->slot] = j;
+                st->digest = digest_event(st->digest, st->n, i, j);
+                st->t += dt;
+            }
+        }
+        if (bad) {
+            out[3] += 1.0;
+            break;
+        }
+        st->n += 1;
+    }
+    free(rates);
+}
+
+/* ------------------------------------------------------------ observables */
+
+/* Sizes of connected clusters of `species` under 1NN adjacency (plain
+ * breadth-first search).  hist[s] counts clusters of size s for
+ * 1 <= s <= max_size; larger clusters are counted in hist[max_size].
+ * Returns the number of clusters. */
+int64_t orc_cluster_hist(const orc_params *p, const uint8_t *occ, int species,
+                         int64_t *hist, int64_t max_size) {
+    int64_t n = 2 * n_cells(p);
+    uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t clusters = 0;
+    for (int64_t s = 0; s <= max_size; s++) hist[s] = 0;
+    for (int64_t s = 0; s < n; s++) {
+        if (occ[s] != species || seen[s]) continue;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = (int32_t)s;
+        seen[s] = 1;
+        while (head < tail) {
+            int32_t a = queue[head++];
+            for (int k = 0; k < 8; k++) {
+                int32_t b = orc_nbr1(p, a, k);
+                if (occ[b] == species && !seen[b]) {
+                    seen[b] = 1;
+                    queue[tail++] = b;
+                }
+            }
+        }
+        hist[tail < max_size ? tail : max_size] += 1;
+        clusters += 1;
+    }
+    free(seen);
+    free(queue);
+    return clusters;
+}
+
+/* ------------------------------------------------------------ surrogate input */
+
+/* Species of the 27 footprint slots of a candidate, in a frame reflected so
+ * that the jump direction becomes (+,+,+):
+ *   slot 0        species A of the jumping atom (site j)
+ *   slots 1..7    N1(i) without j, by reflected direction 0..6
+ *   slots 8..13   N2(i), by reflected 2NN index (+x,-x,+y,-y,+z,-z)
+ *   slots 14..20  N1(j) without i, by reflected direction 1..7
+ *   slots 21..26  N2(j), by reflected 2NN index
+ * Reflecting axis a (where the jump's sign is negative) flips bit (2-a) of
+ * a 1NN direction and swaps the +/- entries of that axis' 2NN pair. */
+void orc_encode_env(const orc_params *p, const uint8_t *occ, int32_t i, int k,
+                    uint8_t out[27]) {
+    int flip = (~k) & 7;
+    int32_t j = orc_nbr1(p, i, k);
+    out[0] = occ[j];
+    for (int d = 0; d < 7; d++) out[1 + d] = occ[orc_nbr1(p, i, d ^ flip)];
+    for (int m = 0; m < 6; m++) {
+        int axis = m >> 1;
+        int flipped = (flip >> (2 - axis)) & 1;
+        out[8 + m] = occ[orc_nbr2(p, i, flipped ? (m ^ 1) : m)];
+        out[21 + m] = occ[orc_nbr2(p, j, flipped ? (m ^ 1) : m)];
+    }
+    for (int d = 1; d < 8; d++) out[13 + d] = occ[orc_nbr1(p, j, d ^ flip)];
+}

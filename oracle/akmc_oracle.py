@@ -1,0 +1,215 @@
+"""ctypes wrapper around the C oracle (akmc_oracle.c).
+
+TEST INFRASTRUCTURE (see oracle/__init__.py).  Inputs come from
+paper_2604_24091_amd.workloads.LatticeSpec objects or plain numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+class OrcParams(C.Structure):
+    _fields_ = [("lx", C.c_int32), ("ly", C.c_int32), ("lz", C.c_int32),
+                ("n_species", C.c_int32),
+                ("eps1", C.c_double * 64), ("eps2", C.c_double * 64),
+                ("e0", C.c_double * 8),
+                ("nu", C.c_double), ("temperature", C.c_double), ("kb", C.c_double),
+                ("seed", C.c_uint64), ("stream_id", C.c_uint64),
+                ("precision", C.c_int32), ("time_mode", C.c_int32)]
+
+
+class OrcEvent(C.Structure):
+    _fields_ = [("n", C.c_int64), ("slot", C.c_int32), ("from_site", C.c_int32),
+                ("to_site", C.c_int32), ("dir", C.c_uint8), ("species", C.c_uint8),
+                ("pad", C.c_uint8 * 2), ("gamma_tot", C.c_double), ("dt", C.c_double)]
+
+
+class OrcState(C.Structure):
+    _fields_ = [("n", C.c_int64), ("t", C.c_double), ("digest", C.c_uint64),
+                ("gamma_tot", C.c_double), ("n_neg_barrier", C.c_int64)]
+
+
+EVENT_DTYPE = np.dtype([("n", "<i8"), ("slot", "<i4"), ("from_site", "<i4"),
+                        ("to_site", "<i4"), ("dir", "u1"), ("species", "u1"),
+                        ("pad", "u1", (2,)), ("gamma_tot", "<f8"), ("dt", "<f8")])
+assert EVENT_DTYPE.itemsize == C.sizeof(OrcEvent) == 40
+
+FNV_OFFSET = 0xCBF29CE484222325
+
+_u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = C.CDLL(path)
+        P = C.POINTER(OrcParams)
+        L.orc_site.argtypes = [P, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_site.restype = C.c_int32
+        L.orc_nbr1.argtypes = [P, C.c_int32, C.c_int]
+        L.orc_nbr1.restype = C.c_int32
+        L.orc_nbr2.argtypes = [P, C.c_int32, C.c_int]
+        L.orc_nbr2.restype = C.c_int32
+        L.orc_delta_e.argtypes = [P, _u8p, C.c_int32, C.c_int]
+        L.orc_delta_e.restype = C.c_double
+        L.orc_candidate.argtypes = [P, _u8p, C.c_int32, C.c_int,
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_candidate.restype = None
+        L.orc_rates_sites.argtypes = [P, _u8p, _i32p, C.c_int64, _f64p, C.c_void_p]
+        L.orc_rates_sites.restype = None
+        L.orc_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
+        L.orc_philox4x64_10.restype = None
+        L.orc_uniforms.argtypes = [C.c_uint64, C.c_uint64, C.c_int64,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_uniforms.restype = None
+        L.orc_fnv1a.argtypes = [C.c_uint64, _u8p, C.c_int64]
+        L.orc_fnv1a.restype = C.c_uint64
+        L.orc_select.argtypes = [_f64p, C.c_int64, C.c_double, C.POINTER(C.c_double)]
+        L.orc_select.restype = C.c_int64
+        L.orc_gamma_tot.argtypes = [P, _u8p, _i32p, C.c_int32]
+        L.orc_gamma_tot.restype = C.c_double
+        L.orc_run.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState),
+                              C.c_int64, C.c_void_p]
+        L.orc_run.restype = C.c_int64
+        L.orc_follow.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState),
+                                 C.c_int64, C.c_void_p, _f64p]
+        L.orc_follow.restype = None
+        L.orc_cluster_hist.argtypes = [P, _u8p, C.c_int, _i64p, C.c_int64]
+        L.orc_cluster_hist.restype = C.c_int64
+        L.orc_encode_env.argtypes = [P, _u8p, C.c_int32, C.c_int, _u8p]
+        L.orc_encode_env.restype = None
+        _lib = L
+    return _lib
+
+
+def make_params(spec, precision: int = 0, time_mode: int = 0,
+                temperature: Optional[float] = None) -> OrcParams:
+    p = OrcParams()
+    p.lx, p.ly, p.lz = (int(v) for v in spec.dims)
+    S = int(spec.n_species)
+    p.n_species = S
+    e1 = np.asarray(spec.eps1, dtype=np.float64).reshape(S, S)
+    e2 = np.asarray(spec.eps2, dtype=np.float64).reshape(S, S)
+    for a in range(S):
+        for b in range(S):
+            p.eps1[a * S + b] = e1[a, b]
+            p.eps2[a * S + b] = e2[a, b]
+    for a, v in enumerate(np.asarray(spec.e0, dtype=np.float64)):
+        p.e0[a] = v
+    p.nu = float(spec.nu)
+    p.temperature = float(spec.temperature if temperature is None else temperature)
+    p.kb = float(spec.kb)
+    p.seed = int(spec.seed) & (2**64 - 1)
+    p.stream_id = int(spec.stream_id) & (2**64 - 1)
+    p.precision = int(precision)
+    p.time_mode = int(time_mode)
+    return p
+
+
+class Oracle:
+    """One lattice state advanced by the plain full-recompute AKMC loop."""
+
+    def __init__(self, spec, precision: int = 0, time_mode: int = 0):
+        self.spec = spec
+        self.p = make_params(spec, precision, time_mode)
+        self.occ = np.ascontiguousarray(spec.occ, dtype=np.uint8).copy()
+        self.slots = np.flatnonzero(self.occ == spec.n_species - 1).astype(np.int32)
+        self.state = OrcState(0, 0.0, FNV_OFFSET, 0.0, 0)
+
+    # geometry --------------------------------------------------------------
+    def nbr1(self, site: int, k: int) -> int:
+        return lib().orc_nbr1(C.byref(self.p), site, k)
+
+    def nbr2(self, site: int, m: int) -> int:
+        return lib().orc_nbr2(C.byref(self.p), site, m)
+
+    # rates -----------------------------------------------------------------
+    def delta_e(self, i: int, k: int, occ=None) -> float:
+        occ = self.occ if occ is None else occ
+        return lib().orc_delta_e(C.byref(self.p), occ, int(i), int(k))
+
+    def rates_sites(self, sites, occ=None):
+        occ = self.occ if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
+        sites = np.ascontiguousarray(sites, dtype=np.int32)
+        n = sites.size
+        rates = np.zeros((n, 8), dtype=np.float64)
+        ea = np.zeros((n, 8), dtype=np.float64)
+        lib().orc_rates_sites(C.byref(self.p), occ, sites, n, rates,
+                              ea.ctypes.data_as(C.c_void_p))
+        return rates, ea
+
+    def rates_vacancies(self):
+        return self.rates_sites(self.slots)
+
+    def gamma_tot(self) -> float:
+        return lib().orc_gamma_tot(C.byref(self.p), self.occ, self.slots, self.slots.size)
+
+    # events ----------------------------------------------------------------
+    def run(self, n_events: int, log: bool = False):
+        buf = np.zeros(max(n_events, 1), dtype=EVENT_DTYPE) if log else None
+        done = lib().orc_run(C.byref(self.p), self.occ, self.slots, self.slots.size,
+                             C.byref(self.state), int(n_events),
+                             buf.ctypes.data_as(C.c_void_p) if log else None)
+        if log:
+            return done, buf[:max(done, 0)]
+        return done
+
+    def follow(self, log_records):
+        recs = np.ascontiguousarray(log_records, dtype=EVENT_DTYPE)
+        out = np.zeros(4, dtype=np.float64)
+        lib().orc_follow(C.byref(self.p), self.occ, self.slots, self.slots.size,
+                         C.byref(self.state), recs.size,
+                         recs.ctypes.data_as(C.c_void_p), out)
+        return {"max_select_violation": out[0], "max_gamma_rel": out[1],
+                "max_dt_rel": out[2], "mismatches": int(out[3])}
+
+    def cluster_hist(self, species: int = 1, max_size: int = 64, occ=None):
+        occ = self.occ if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
+        hist = np.zeros(max_size + 1, dtype=np.int64)
+        n = lib().orc_cluster_hist(C.byref(self.p), occ, int(species), hist, max_size)
+        return n, hist
+
+    def encode_env(self, i: int, k: int, occ=None):
+        occ = self.occ if occ is None else occ
+        out = np.zeros(27, dtype=np.uint8)
+        lib().orc_encode_env(C.byref(self.p), occ, int(i), int(k), out)
+        return out
+
+
+def philox(counter, key):
+    ctr = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    out = np.zeros(4, dtype=np.uint64)
+    lib().orc_philox4x64_10(ctr, k, out)
+    return out
+
+
+def uniforms(seed: int, stream_id: int, n: int):
+    u1, u2 = C.c_double(), C.c_double()
+    lib().orc_uniforms(seed, stream_id, n, C.byref(u1), C.byref(u2))
+    return u1.value, u2.value
+
+
+def fnv1a(data: bytes, h: int = FNV_OFFSET) -> int:
+    arr = np.frombuffer(bytes(data), dtype=np.uint8).copy() if data else np.zeros(1, np.uint8)
+    return lib().orc_fnv1a(h, arr, len(data))
+
+
+def select(rates, u1: float):
+    r = np.ascontiguousarray(rates, dtype=np.float64)
+    g = C.c_double()
+    c = lib().orc_select(r, r.size, float(u1), C.byref(g))
+    return c, g.value

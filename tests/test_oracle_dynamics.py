@@ -1,0 +1,199 @@
+"""Pins of the oracle's random stream, digest, selection, time and
+trajectory (orc_philox4x64_10, orc_uniforms, orc_fnv1a, orc_select, orc_run).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2604_24091_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_philox_known_answers(oracle_mod):
+    with open(os.path.join(GOLDEN, "philox4x64_10_kat.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        vals = [int(v, 16) for v in r]
+        out = oracle_mod.philox(vals[0:4], vals[4:6])
+        assert [int(v) for v in out] == vals[6:10]
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 1000, 2**33 + 17])
+def test_philox_equals_numpy(oracle_mod, n):
+    """numpy's Philox pre-increments its 256-bit counter, so block n is
+    numpy's output for counter n - 1 (wrapping for n = 0)."""
+    key = np.array([0x1234_5678_9ABC_DEF0, 42], dtype=np.uint64)
+    c = (n - 1) % 2**256
+    ctr = np.array([(c >> (64 * w)) & (2**64 - 1) for w in range(4)], dtype=np.uint64)
+    g = np.random.Philox(counter=ctr, key=key)
+    ref = [int(v) for v in g.random_raw(4)]
+    assert [int(v) for v in oracle_mod.philox([n, 0, 0, 0], key)] == ref
+
+
+def test_uniform_mapping(oracle_mod):
+    key = (99, 3)
+    for n in (0, 5, 77):
+        x = oracle_mod.philox([n, 0, 0, 0], key)
+        u1, u2 = oracle_mod.uniforms(key[0], key[1], n)
+        assert u1 == (int(x[0]) >> 11) * 2.0**-53
+        assert u2 == ((int(x[1]) >> 11) + 1) * 2.0**-53
+        assert 0.0 <= u1 < 1.0 and 0.0 < u2 <= 1.0
+
+
+def test_fnv1a_published_vectors(oracle_mod):
+    with open(os.path.join(GOLDEN, "fnv1a64.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            text, h = line.rsplit(" ", 1)
+            data = text.strip().strip('"').encode()
+            assert oracle_mod.fnv1a(data) == int(h, 16)
+
+
+def test_selection_frequencies_follow_rates(oracle_mod):
+    """Eq. 2 competition: candidate c is chosen with probability r_c/G;
+    masked (zero-rate) candidates are never chosen."""
+    rng = np.random.default_rng(5)
+    rates = rng.uniform(0.0, 1.0, 40) ** 4 * 1e9
+    rates[[3, 17, 18, 39]] = 0.0
+    draws = 200_000
+    u = rng.random(draws)
+    counts = np.zeros(rates.size, dtype=np.int64)
+    for x in u:
+        c, g = oracle_mod.select(rates, x)
+        counts[c] += 1
+    assert counts[[3, 17, 18, 39]].sum() == 0
+    m = rates > 0
+    expected = rates[m] / rates.sum() * draws
+    chi2, p = stats.chisquare(counts[m], expected)
+    assert p > 1e-4, (chi2, p)
+
+
+def test_selection_boundaries(oracle_mod):
+    rates = np.array([0.0, 0.0, 2.0, 0.0, 5.0, 1.0, 0.0])
+    assert oracle_mod.select(rates, 0.0)[0] == 2
+    assert oracle_mod.select(rates, 1.0 - 2.0**-53)[0] == 5
+    assert oracle_mod.select(rates, 0.25)[0] == 4        # 0.25*8 = 2 is not > 2
+    assert oracle_mod.select(np.zeros(5), 0.3)[0] == -1   # frozen
+
+
+def _single_vacancy_fe(dims=(8, 8, 8), stream=0, seed=7):
+    spec = W.pure_fe(dims, n_vac=1, seed=seed)
+    spec.stream_id = stream
+    return spec
+
+
+def test_time_increments_are_exponential(oracle_mod):
+    """Gamma_tot * dt ~ Exp(1) (KS test); mean 1 (Eq. 5 => E[dt] = 1/G)."""
+    spec = W.fe_cu_2k()
+    o = oracle_mod.Oracle(spec)
+    done, log = o.run(20_000, log=True)
+    x = log["dt"] * log["gamma_tot"]
+    assert stats.kstest(x, "expon").pvalue > 1e-3
+    assert abs(x.mean() - 1.0) < 5 / math.sqrt(x.size)
+    o2 = oracle_mod.Oracle(spec, time_mode=1)
+    _, log2 = o2.run(100, log=True)
+    np.testing.assert_array_equal(log2["dt"], 1.0 / log2["gamma_tot"])
+
+
+def test_pure_fe_single_vacancy_diffusion(oracle_mod):
+    """Uncorrelated random walk on BCC: <R^2(n)> = 3 n (a/2)^2, jump
+    directions uniform over 8, E[t_n] = n/G with G = 8 nu exp(-E0/kT);
+    hence D_V = a^2 nu exp(-E0/kT) (1.389e-8 cm^2/s at 563 K, E0 = 0.62 eV,
+    nu = 6e12 Hz, a = 2.866 A)."""
+    spec = _single_vacancy_fe()
+    o = oracle_mod.Oracle(spec)
+    n_ev, win = 200_000, 100
+    done, log = o.run(n_ev, log=True)
+    assert done == n_ev
+    sx = np.where((log["dir"] >> 2) & 1, 1, -1)
+    sy = np.where((log["dir"] >> 1) & 1, 1, -1)
+    sz = np.where(log["dir"] & 1, 1, -1)
+    disp = np.stack([sx, sy, sz], 1).reshape(-1, win, 3).sum(1)
+    r2 = (disp ** 2).sum(1)
+    mean, sem = r2.mean(), math.sqrt(6.0) * win / math.sqrt(r2.size)
+    assert abs(mean - 3 * win) < 5 * sem
+    counts = np.bincount(log["dir"], minlength=8)
+    assert stats.chisquare(counts).pvalue > 1e-4
+    kt = spec.kb * spec.temperature
+    r = spec.nu * math.exp(-spec.e0[0] / kt)
+    G = 8 * r
+    np.testing.assert_allclose(log["gamma_tot"], G, rtol=1e-14)
+    t = log["dt"].sum()
+    assert abs(t - n_ev / G) < 5 * math.sqrt(n_ev) / G
+    a_cm = 2.866e-8
+    D = (3 * win * (a_cm / 2) ** 2 * r2.mean() / (3 * win)) / (6 * win / G)
+    assert D == pytest.approx(a_cm ** 2 * r, rel=0.05)
+    assert a_cm ** 2 * r == pytest.approx(1.389e-8, rel=1e-3)
+
+
+def test_conservation_and_log_consistency(oracle_mod):
+    rng = np.random.default_rng(61)
+    spec = W.random_lattice(rng, (6, 6, 6), 5, 9, solute_total=0.2)
+    o = oracle_mod.Oracle(spec)
+    start_counts = np.bincount(spec.occ, minlength=5)
+    done, log = o.run(3000, log=True)
+    assert done == 3000
+    assert np.array_equal(np.bincount(o.occ, minlength=5), start_counts)
+    assert np.array_equal(np.sort(o.slots), np.flatnonzero(o.occ == 4))
+    # Each slot's vacancy path is continuous and every move is a 1NN jump
+    # onto an atom (never onto another vacancy).
+    where = np.flatnonzero(spec.occ == 4).astype(np.int64)
+    for ev in log:
+        assert where[ev["slot"]] == ev["from_site"]
+        assert o.nbr1(int(ev["from_site"]), int(ev["dir"])) == ev["to_site"]
+        assert ev["species"] != 4
+        where[ev["slot"]] = ev["to_site"]
+    assert np.array_equal(where, o.slots)
+    assert np.array_equal(log["n"], np.arange(3000))
+
+
+def test_chunked_run_equals_single_run(oracle_mod):
+    spec = W.fe_cu_2k()
+    a = oracle_mod.Oracle(spec)
+    a.run(1234)
+    a.run(766)
+    b = oracle_mod.Oracle(spec)
+    b.run(2000)
+    assert np.array_equal(a.occ, b.occ) and np.array_equal(a.slots, b.slots)
+    assert a.state.digest == b.state.digest and a.state.t == b.state.t
+    assert a.state.n == b.state.n == 2000
+
+
+def test_frozen_state_reports(oracle_mod):
+    spec = W.pure_fe((3, 3, 3), n_vac=0)
+    spec.occ[:] = 2                       # every site a vacancy: nothing can move
+    o = oracle_mod.Oracle(spec)
+    assert o.run(5) == -4
+    assert o.state.n == 0
+
+
+def test_digest_definition(oracle_mod):
+    spec = W.fe_cu_2k()
+    o = oracle_mod.Oracle(spec)
+    _, log = o.run(50, log=True)
+    h = oracle_mod.FNV_OFFSET
+    for ev in log:
+        b = (int(ev["n"]).to_bytes(8, "little") + int(ev["from_site"]).to_bytes(4, "little")
+             + int(ev["to_site"]).to_bytes(4, "little"))
+        h = oracle_mod.fnv1a(b, h)
+    assert h == o.state.digest
+
+
+def test_follow_accepts_own_log_and_rejects_a_wrong_choice(oracle_mod):
+    rng = np.random.default_rng(71)
+    spec = W.random_lattice(rng, (6, 6, 6), 5, 6, solute_total=0.2)
+    o = oracle_mod.Oracle(spec)
+    _, log = o.run(500, log=True)
+    f = oracle_mod.Oracle(spec).follow(log)
+    assert f["mismatches"] == 0 and f["max_select_violation"] == 0.0
+    assert f["max_dt_rel"] == 0.0 and f["max_gamma_rel"] == 0.0
+    bad = log.copy()
+    bad[100]["dir"] = (bad[100]["dir"] + 1) % 8
+    g = oracle_mod.Oracle(spec).follow(bad)
+    assert g["mismatches"] == 1 or g["max_select_violation"] > 0.0
