@@ -1,0 +1,237 @@
+/*
+ * akmc.h -- C interface of the MI355X (gfx950) vacancy-jump AKMC library.
+ *
+ * The library runs the classical atomistic kinetic Monte Carlo step that
+ * the paper (Sec. III-B1) describes as the memory-bound baseline of its
+ * method: before every event, every migration direction of every vacancy
+ * is evaluated (pair-bond energy change, Kang-Weinberg barrier, Arrhenius
+ * rate of Eq. 8, feasibility mask of Eq. 1), one event is drawn with
+ * probability proportional to its rate (the system-wide competition of
+ * Eq. 2), physical time advances by an increment inversely proportional to
+ * the total rate (Sec. II; mean 1/Gamma_tot by Eq. 5), the atom and the
+ * vacancy swap, and the rates near the jump are refreshed.
+ *
+ * Conventions shared by every call (they are readings of the paper, which
+ * does not state a lattice or an energy model):
+ *   - BCC lattice of lx*ly*lz cubic cells, periodic, two sites per cell,
+ *     each edge >= 3 cells.  Site index
+ *         site = b*lx*ly*lz + (z*ly + y)*lx + x,
+ *     b = 0 for the cube corner, b = 1 for the body centre.
+ *   - Occupancy: one uint8 species code per site, codes 0..S-1, the last
+ *     code S-1 is the vacancy.
+ *   - First-neighbour direction k = 4*[sx>0] + 2*[sy>0] + [sz>0] for the
+ *     displacement (sx, sy, sz)*a/2; candidate c = 8*slot + k.
+ *   - Energy: symmetric 1NN and 2NN pair energies eps1, eps2 (S x S, eV,
+ *     vacancy rows included).  The energy change of "vacancy at i <- atom
+ *     of species A at j" is built from integer species counts of the bonds
+ *     it changes times D_k[A][s] = eps_k[A][s] - eps_k[S-1][s].
+ *   - Barrier Ea = e0[A] + dE/2 (no clamp); rate = nu * exp(-Ea/(kb*T)).
+ *     A jump onto another vacancy is inadmissible: rate +0, Ea = +inf.
+ *   - Random stream: Philox4x64-10, key (seed, stream_id), counter
+ *     (n, 0, 0, 0) for global event index n; u1 = (x0 >> 11) * 2^-53,
+ *     u2 = ((x1 >> 11) + 1) * 2^-53.  dt = -ln(u2)/Gamma_tot.
+ *   - Vacancy slots are numbered by ascending site at creation; a slot
+ *     follows its vacancy.
+ *   - Digest: FNV-1a 64 over the little-endian bytes of
+ *     (n:int64, from_site:int32, to_site:int32) of every event.
+ *
+ * Memory: the library allocates no device memory.  The caller owns a
+ * device workspace (sized by the *_workspace_bytes calls) and every device
+ * output buffer; host pointers are only read or written during the call.
+ * Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ * void*); calls return before the GPU finishes unless stated otherwise.
+ *
+ * Errors: every call returns an akmc_status.  Nothing throws or aborts
+ * across this interface.  akmc_last_error() describes the last failure of
+ * the calling thread.  Calls on one handle are not thread-safe.
+ */
+#ifndef AKMC_H
+#define AKMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t akmc_status;
+#define AKMC_OK                 0
+#define AKMC_ERR_INVALID       -1   /* bad argument (message says which) */
+#define AKMC_ERR_WORKSPACE     -2   /* workspace smaller than required */
+#define AKMC_ERR_HIP           -3   /* a HIP runtime call failed */
+#define AKMC_ERR_FROZEN        -4   /* total rate is zero: no event possible */
+#define AKMC_ERR_UNSUPPORTED   -5   /* valid but outside the built limits */
+
+#define AKMC_MAX_SPECIES        8
+#define AKMC_MAX_VACANCIES    512   /* per lattice */
+
+/* precision */
+#define AKMC_FP64 0     /* energies, barriers, rates, sums and time in binary64 */
+#define AKMC_FP32 1     /* energies, barriers, rates in binary32; sums, time binary64 */
+/* refresh */
+#define AKMC_REFRESH_LOCAL 0  /* after a jump, refresh the slots near it */
+#define AKMC_REFRESH_FULL  1  /* recompute every slot (same results, slower) */
+/* time_mode */
+#define AKMC_TIME_STOCHASTIC 0  /* dt = -ln(u2) / Gamma_tot */
+#define AKMC_TIME_MEAN       1  /* dt = 1 / Gamma_tot */
+/* barrier_model */
+#define AKMC_BARRIER_PAIR 0
+#define AKMC_BARRIER_MLP  1   /* needs akmc_mlp_attach */
+/* rates_eval mode */
+#define AKMC_RATES_VACANCIES 0  /* current slots      -> [n_vac][8]   */
+#define AKMC_RATES_SITES     1  /* listed sites       -> [n_sites][8] */
+#define AKMC_RATES_ALL_SITES 2  /* every lattice site -> [N][8]       */
+
+/* Lattice and model parameters.  All host values are copied at create. */
+typedef struct akmc_params {
+    int32_t lx, ly, lz;        /* cubic cells per axis, each >= 3 */
+    int32_t n_species;         /* S, 2..8; code S-1 is the vacancy */
+    double eps1[64];           /* 1NN pair energies, S*S row-major, symmetric, eV */
+    double eps2[64];           /* 2NN pair energies, same layout */
+    double e0[8];              /* barrier offset per migrating species 0..S-2, eV */
+    double nu;                 /* attempt frequency, Hz, > 0 */
+    double temperature;        /* K, > 0 */
+    double kb;                 /* Boltzmann constant, eV/K (8.617333262e-5) */
+    uint64_t seed;             /* Philox key word 0 */
+    uint64_t stream_id;        /* Philox key word 1 */
+    int64_t event_counter0;    /* global index of the next event (resume) */
+    double time0;              /* physical time at create, s (resume) */
+    uint64_t digest0;          /* digest at create; 0 selects the FNV offset basis */
+    int32_t precision;         /* AKMC_FP64 or AKMC_FP32 */
+    int32_t refresh;           /* AKMC_REFRESH_LOCAL or AKMC_REFRESH_FULL */
+    int32_t time_mode;         /* AKMC_TIME_STOCHASTIC or AKMC_TIME_MEAN */
+    int32_t barrier_model;     /* AKMC_BARRIER_PAIR or AKMC_BARRIER_MLP */
+} akmc_params;
+
+/* One executed event (40 bytes). */
+typedef struct akmc_event {
+    int64_t n;                 /* global event index */
+    int32_t slot;              /* vacancy slot that moved */
+    int32_t from_site;         /* vacancy site before the jump */
+    int32_t to_site;           /* vacancy site after the jump */
+    uint8_t dir;               /* first-neighbour direction 0..7 */
+    uint8_t species;           /* species of the atom that moved */
+    uint8_t pad[2];
+    double gamma_tot;          /* total rate of the state before the jump, Hz */
+    double dt;                 /* time increment, s */
+} akmc_event;
+
+typedef struct akmc_summary {
+    double t;                  /* physical time, s */
+    int64_t n_events;          /* global index of the next event */
+    double gamma_tot;          /* total rate of the current state, Hz */
+    uint64_t digest;
+    int64_t species_count[8];  /* sites per species code */
+    int64_t n_neg_barrier;     /* current candidates with Ea < 0 */
+    int64_t n_ood;             /* surrogate evaluations that fell back to the pair model */
+    int32_t n_vacancies;
+    int32_t frozen;            /* 1 if the last kmc_step stopped on Gamma_tot = 0 */
+} akmc_summary;
+
+typedef struct akmc_lattice *akmc_handle;
+
+/* Device bytes the workspace of one lattice with these parameters and
+ * n_vac vacancies needs.  Defined for: the state that lattice_create
+ * fills.  Errors: AKMC_ERR_INVALID for bad parameters. */
+akmc_status akmc_workspace_bytes(const akmc_params *p, int32_t n_vac, size_t *bytes);
+
+/* Creates a lattice.  occ_host: uint8[2*lx*ly*lz] host occupancy (copied).
+ * slot_sites_host: int32[n_vac] site of every vacancy slot, in slot order
+ * (copied), or NULL for ascending site order; a snapshot taken with
+ * state_read and passed back here with its event counter, time and digest
+ * continues exactly like the uninterrupted run.  d_ws: device workspace of
+ * ws_bytes (borrowed; must outlive the handle, 256-byte aligned).
+ * hip_stream: hipStream_t or NULL for the default stream.  Errors:
+ * INVALID (bad parameters, species code >= S, a slot list that is not the
+ * set of vacancy sites), UNSUPPORTED (more than AKMC_MAX_VACANCIES),
+ * WORKSPACE, HIP. */
+akmc_status akmc_lattice_create(const akmc_params *p, const uint8_t *occ_host,
+                                const int32_t *slot_sites_host, void *d_ws,
+                                size_t ws_bytes, void *hip_stream, akmc_handle *out);
+
+/* Rates of the Eq. 8 law for a vacancy placed at each site of the mode's
+ * site set (that site counts as a vacancy whatever it holds), in the
+ * 8 directions: d_rates_out[site_index][k].  Element type is double for
+ * AKMC_FP64 and float for AKMC_FP32.  d_ea_out (same type and shape, may
+ * be NULL) receives the barriers.  d_sites: device int32 site list for
+ * AKMC_RATES_SITES (ignored otherwise); a listed site outside [0, N) gets
+ * NaN rates and barriers.  Asynchronous.  Errors: INVALID (mode, NULL
+ * output or site list). */
+akmc_status akmc_rates_eval(akmc_handle h, int32_t mode, const int32_t *d_sites,
+                            int64_t n_sites, void *d_rates_out, void *d_ea_out);
+
+/* Performs exactly n_events residence-time events on the device with no
+ * host round trip.  d_log: device array of n_events records, or NULL.
+ * kmc_step(a) followed by kmc_step(b) gives the same state, bit for bit,
+ * as kmc_step(a + b).  If the total rate becomes zero the lattice stops
+ * where it is and state_read reports frozen = 1; further steps do nothing.
+ * A lattice without vacancies returns AKMC_ERR_FROZEN.  Asynchronous. */
+akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log);
+
+/* Synchronises the handle's stream and copies the state out.  occ_host
+ * (uint8[N]) and slot_sites_host (int32[n_vac]) may be NULL; out may be
+ * NULL. */
+akmc_status akmc_state_read(akmc_handle h, uint8_t *occ_host, int32_t *slot_sites_host,
+                            akmc_summary *out);
+
+/* Releases the host-side handle.  Does not free d_ws. */
+akmc_status akmc_lattice_destroy(akmc_handle h);
+
+/* -------------------------------------------------------------- batches */
+
+/* Independent replicas in one persistent launch: the paper's voxel
+ * ensemble (Sec. III-C1), each replica a periodic lattice evolved with no
+ * communication, scheduled heaviest first from a device work queue
+ * (Sec. III-C2, priority of Eq. 10).  Replica r gives bit for bit the
+ * same state as a standalone handle with the same parameters. */
+typedef struct akmc_batch_s *akmc_batch;
+
+typedef struct akmc_schedule {
+    int32_t group_lanes;       /* lanes serving one replica: 8, 16, 32 or 64 */
+    int32_t waves_per_block;   /* 1, 2 or 4 */
+    int32_t blocks;            /* persistent blocks; 0 = one per 256 CUs worth */
+    int32_t use_graph;         /* replay the chunk launches from a hipGraph */
+    int64_t chunk_events;      /* events per replica per launch, > 0 */
+} akmc_schedule;
+
+/* n_vac[r] vacancies in replica r.  Errors: INVALID. */
+akmc_status akmc_batch_workspace_bytes(int32_t n_rep, const akmc_params *p,
+                                       const int32_t *n_vac, size_t *bytes);
+
+/* p[n_rep] parameters (each replica's own lattice, temperature and Philox
+ * key); occ_host[r] its occupancy; slot_sites_host NULL, or per replica a
+ * slot list or NULL (as in lattice_create).  Same ownership rules as
+ * lattice_create. */
+akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p,
+                              const uint8_t *const *occ_host,
+                              const int32_t *const *slot_sites_host, void *d_ws,
+                              size_t ws_bytes, void *hip_stream, akmc_batch *out);
+
+/* Sets the launch schedule (see akmc_batch_autotune).  Results do not
+ * depend on the schedule. */
+akmc_status akmc_batch_set_schedule(akmc_batch b, const akmc_schedule *s);
+
+/* Runs n_events events in every replica.  Asynchronous. */
+akmc_status akmc_batch_step(akmc_batch b, int64_t n_events_per_replica);
+
+/* Times candidate schedules on the live batch (each trial advances every
+ * replica by trial_events events; results do not depend on the schedule),
+ * keeps the fastest and returns it.  Synchronises the stream. */
+akmc_status akmc_batch_autotune(akmc_batch b, int64_t trial_events, akmc_schedule *chosen);
+
+/* State of replica r (synchronises the stream). */
+akmc_status akmc_batch_state_read(akmc_batch b, int32_t r, uint8_t *occ_host,
+                                  int32_t *slot_sites_host, akmc_summary *out);
+
+akmc_status akmc_batch_destroy(akmc_batch b);
+
+/* ------------------------------------------------------------ messages */
+
+const char *akmc_status_string(akmc_status s);
+const char *akmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AKMC_H */

@@ -1,0 +1,329 @@
+"""Python binding of libakmc.so (include/akmc.h).
+
+Argument marshalling only: every step of the path runs in the HIP
+library.  Device buffers are torch tensors on a ROCm device (PyTorch owns
+device memory); the HIP stream is torch's current stream unless given.
+Importing this module never falls back to anything: if libakmc.so is
+missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libakmc.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "akmc.h")
+
+OK, ERR_INVALID, ERR_WORKSPACE, ERR_HIP, ERR_FROZEN, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+FP64, FP32 = 0, 1
+REFRESH_LOCAL, REFRESH_FULL = 0, 1
+TIME_STOCHASTIC, TIME_MEAN = 0, 1
+BARRIER_PAIR, BARRIER_MLP = 0, 1
+RATES_VACANCIES, RATES_SITES, RATES_ALL_SITES = 0, 1, 2
+MAX_VACANCIES = 512
+
+
+class Params(C.Structure):
+    _fields_ = [("lx", C.c_int32), ("ly", C.c_int32), ("lz", C.c_int32),
+                ("n_species", C.c_int32),
+                ("eps1", C.c_double * 64), ("eps2", C.c_double * 64), ("e0", C.c_double * 8),
+                ("nu", C.c_double), ("temperature", C.c_double), ("kb", C.c_double),
+                ("seed", C.c_uint64), ("stream_id", C.c_uint64),
+                ("event_counter0", C.c_int64), ("time0", C.c_double), ("digest0", C.c_uint64),
+                ("precision", C.c_int32), ("refresh", C.c_int32), ("time_mode", C.c_int32),
+                ("barrier_model", C.c_int32)]
+
+
+class Event(C.Structure):
+    _fields_ = [("n", C.c_int64), ("slot", C.c_int32), ("from_site", C.c_int32),
+                ("to_site", C.c_int32), ("dir", C.c_uint8), ("species", C.c_uint8),
+                ("pad", C.c_uint8 * 2), ("gamma_tot", C.c_double), ("dt", C.c_double)]
+
+
+class Summary(C.Structure):
+    _fields_ = [("t", C.c_double), ("n_events", C.c_int64), ("gamma_tot", C.c_double),
+                ("digest", C.c_uint64), ("species_count", C.c_int64 * 8),
+                ("n_neg_barrier", C.c_int64), ("n_ood", C.c_int64),
+                ("n_vacancies", C.c_int32), ("frozen", C.c_int32)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("group_lanes", C.c_int32), ("waves_per_block", C.c_int32),
+                ("blocks", C.c_int32), ("use_graph", C.c_int32), ("chunk_events", C.c_int64)]
+
+
+EVENT_DTYPE = np.dtype([("n", "<i8"), ("slot", "<i4"), ("from_site", "<i4"),
+                        ("to_site", "<i4"), ("dir", "u1"), ("species", "u1"),
+                        ("pad", "u1", (2,)), ("gamma_tot", "<f8"), ("dt", "<f8")])
+assert EVENT_DTYPE.itemsize == C.sizeof(Event) == 40
+
+
+class AkmcError(RuntimeError):
+    def __init__(self, status: int, what: str, detail: str):
+        super().__init__("%s failed: %s (%s)" % (what, status_string(status), detail))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libakmc.so is not built (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, sz = C.c_void_p, C.c_size_t
+        P = C.POINTER(Params)
+        L.akmc_workspace_bytes.argtypes = [P, C.c_int32, C.POINTER(sz)]
+        L.akmc_lattice_create.argtypes = [P, vp, vp, vp, sz, vp, C.POINTER(vp)]
+        L.akmc_rates_eval.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, vp]
+        L.akmc_kmc_step.argtypes = [vp, C.c_int64, vp]
+        L.akmc_state_read.argtypes = [vp, vp, vp, C.POINTER(Summary)]
+        L.akmc_lattice_destroy.argtypes = [vp]
+        L.akmc_batch_workspace_bytes.argtypes = [C.c_int32, P, vp, C.POINTER(sz)]
+        L.akmc_batch_create.argtypes = [C.c_int32, P, vp, vp, vp, sz, vp, C.POINTER(vp)]
+        L.akmc_batch_set_schedule.argtypes = [vp, C.POINTER(Schedule)]
+        L.akmc_batch_step.argtypes = [vp, C.c_int64]
+        L.akmc_batch_autotune.argtypes = [vp, C.c_int64, C.POINTER(Schedule)]
+        L.akmc_batch_state_read.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(Summary)]
+        L.akmc_batch_destroy.argtypes = [vp]
+        L.akmc_status_string.argtypes = [C.c_int32]
+        L.akmc_status_string.restype = C.c_char_p
+        L.akmc_last_error.restype = C.c_char_p
+        for name in ("akmc_workspace_bytes", "akmc_lattice_create", "akmc_rates_eval",
+                     "akmc_kmc_step", "akmc_state_read", "akmc_lattice_destroy",
+                     "akmc_batch_workspace_bytes", "akmc_batch_create", "akmc_batch_set_schedule",
+                     "akmc_batch_step", "akmc_batch_autotune", "akmc_batch_state_read",
+                     "akmc_batch_destroy"):
+            getattr(L, name).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list:
+    """Names of the functions include/akmc.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:akmc_status|const char \*)\s*(akmc_\w+)\s*\(", text, re.M)))
+
+
+def status_string(s: int) -> str:
+    return lib().akmc_status_string(s).decode()
+
+
+def last_error() -> str:
+    return lib().akmc_last_error().decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise AkmcError(status, what, last_error())
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def make_params(spec, precision: int = FP64, refresh: int = REFRESH_LOCAL,
+                time_mode: int = TIME_STOCHASTIC, barrier_model: int = BARRIER_PAIR,
+                event_counter0: int = 0, time0: float = 0.0, digest0: int = 0) -> Params:
+    """Params from a workloads.LatticeSpec (or any object with the same fields)."""
+    p = Params()
+    p.lx, p.ly, p.lz = (int(v) for v in spec.dims)
+    S = int(spec.n_species)
+    p.n_species = S
+    e1 = np.asarray(spec.eps1, dtype=np.float64).reshape(S, S)
+    e2 = np.asarray(spec.eps2, dtype=np.float64).reshape(S, S)
+    for a in range(S):
+        for b in range(S):
+            p.eps1[a * S + b] = e1[a, b]
+            p.eps2[a * S + b] = e2[a, b]
+    for a, v in enumerate(np.asarray(spec.e0, dtype=np.float64)):
+        p.e0[a] = v
+    p.nu = float(spec.nu)
+    p.temperature = float(spec.temperature)
+    p.kb = float(spec.kb)
+    p.seed = int(spec.seed) & (2**64 - 1)
+    p.stream_id = int(spec.stream_id) & (2**64 - 1)
+    p.event_counter0 = int(event_counter0)
+    p.time0 = float(time0)
+    p.digest0 = int(digest0) & (2**64 - 1)
+    p.precision = int(precision)
+    p.refresh = int(refresh)
+    p.time_mode = int(time_mode)
+    p.barrier_model = int(barrier_model)
+    return p
+
+
+# ------------------------------------------------------------- C calls
+
+def workspace_bytes(params: Params, n_vac: int) -> int:
+    n = C.c_size_t()
+    _check(lib().akmc_workspace_bytes(C.byref(params), int(n_vac), C.byref(n)), "workspace_bytes")
+    return n.value
+
+
+def lattice_create(params: Params, occ_host: np.ndarray, ws, stream=None,
+                   slot_sites: Optional[np.ndarray] = None) -> int:
+    occ = np.ascontiguousarray(occ_host, dtype=np.uint8)
+    sl = None if slot_sites is None else np.ascontiguousarray(slot_sites, dtype=np.int32)
+    h = C.c_void_p()
+    _check(lib().akmc_lattice_create(C.byref(params), occ.ctypes.data,
+                                     None if sl is None else sl.ctypes.data, _ptr(ws), ws.numel(),
+                                     _stream(stream), C.byref(h)), "lattice_create")
+    return h.value
+
+
+def rates_eval(h: int, mode: int, sites, n_sites: int, rates_out, ea_out=None):
+    _check(lib().akmc_rates_eval(h, int(mode), _ptr(sites), int(n_sites), _ptr(rates_out),
+                                 _ptr(ea_out)), "rates_eval")
+
+
+def kmc_step(h: int, n_events: int, log=None):
+    _check(lib().akmc_kmc_step(h, int(n_events), _ptr(log)), "kmc_step")
+
+
+def state_read(h: int, occ_host: Optional[np.ndarray] = None,
+               slots_host: Optional[np.ndarray] = None) -> Summary:
+    s = Summary()
+    _check(lib().akmc_state_read(h, None if occ_host is None else occ_host.ctypes.data,
+                                 None if slots_host is None else slots_host.ctypes.data,
+                                 C.byref(s)), "state_read")
+    return s
+
+
+def lattice_destroy(h: int):
+    _check(lib().akmc_lattice_destroy(h), "lattice_destroy")
+
+
+def batch_workspace_bytes(params: Sequence[Params], n_vac: Sequence[int]) -> int:
+    arr = (Params * len(params))(*params)
+    nv = np.ascontiguousarray(n_vac, dtype=np.int32)
+    n = C.c_size_t()
+    _check(lib().akmc_batch_workspace_bytes(len(params), arr, nv.ctypes.data, C.byref(n)),
+           "batch_workspace_bytes")
+    return n.value
+
+
+def batch_create(params: Sequence[Params], occs: Sequence[np.ndarray], ws, stream=None,
+                 slot_sites: Optional[Sequence] = None) -> int:
+    arr = (Params * len(params))(*params)
+    occs = [np.ascontiguousarray(o, dtype=np.uint8) for o in occs]
+    ptrs = (C.c_void_p * len(occs))(*[o.ctypes.data for o in occs])
+    sptrs = None
+    if slot_sites is not None:
+        sl = [None if x is None else np.ascontiguousarray(x, dtype=np.int32) for x in slot_sites]
+        sptrs = (C.c_void_p * len(sl))(*[None if x is None else x.ctypes.data for x in sl])
+    b = C.c_void_p()
+    _check(lib().akmc_batch_create(len(params), arr, ptrs, sptrs, _ptr(ws), ws.numel(),
+                                   _stream(stream), C.byref(b)), "batch_create")
+    return b.value
+
+
+def batch_set_schedule(b: int, sched: Schedule):
+    _check(lib().akmc_batch_set_schedule(b, C.byref(sched)), "batch_set_schedule")
+
+
+def batch_step(b: int, n_events_per_replica: int):
+    _check(lib().akmc_batch_step(b, int(n_events_per_replica)), "batch_step")
+
+
+def batch_autotune(b: int, trial_events: int) -> Schedule:
+    s = Schedule()
+    _check(lib().akmc_batch_autotune(b, int(trial_events), C.byref(s)), "batch_autotune")
+    return s
+
+
+def batch_state_read(b: int, r: int, occ_host: Optional[np.ndarray] = None,
+                     slots_host: Optional[np.ndarray] = None) -> Summary:
+    s = Summary()
+    _check(lib().akmc_batch_state_read(b, int(r), None if occ_host is None else occ_host.ctypes.data,
+                                       None if slots_host is None else slots_host.ctypes.data,
+                                       C.byref(s)), "batch_state_read")
+    return s
+
+
+def batch_destroy(b: int):
+    _check(lib().akmc_batch_destroy(b), "batch_destroy")
+
+
+# ------------------------------------------------------ conveniences
+
+class Lattice:
+    """One lattice on the current ROCm device (workspace owned by torch)."""
+
+    def __init__(self, spec, device="cuda", stream=None, slot_sites=None, **kw):
+        import torch
+        self.spec = spec
+        self.params = make_params(spec, **kw)
+        self.n_vac = int(np.count_nonzero(spec.occ == spec.n_species - 1))
+        nbytes = workspace_bytes(self.params, self.n_vac)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream
+        self.h = lattice_create(self.params, spec.occ, self.ws, stream, slot_sites)
+        self.n_sites = spec.n_sites
+
+    def close(self):
+        if getattr(self, "h", None):
+            lattice_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rate_dtype(self):
+        import torch
+        return torch.float32 if self.params.precision == FP32 else torch.float64
+
+    def rates(self, mode=RATES_VACANCIES, sites=None, with_ea=False):
+        import torch
+        dev = self.ws.device
+        if mode == RATES_VACANCIES:
+            n = self.n_vac
+        elif mode == RATES_ALL_SITES:
+            n = self.n_sites
+        else:
+            sites = torch.as_tensor(np.asarray(sites, dtype=np.int32), device=dev)
+            n = sites.numel()
+        out = torch.empty((n, 8), dtype=self.rate_dtype(), device=dev)
+        ea = torch.empty_like(out) if with_ea else None
+        rates_eval(self.h, mode, sites, n, out, ea)
+        return (out, ea) if with_ea else out
+
+    def step(self, n_events: int, log: bool = False):
+        import torch
+        buf = None
+        if log:
+            buf = torch.empty((max(n_events, 1), 40), dtype=torch.uint8, device=self.ws.device)
+        kmc_step(self.h, n_events, buf)
+        return buf
+
+    def read(self):
+        occ = np.empty(self.n_sites, dtype=np.uint8)
+        slots = np.empty(max(self.n_vac, 1), dtype=np.int32)
+        s = state_read(self.h, occ, slots)
+        return occ, slots[:self.n_vac], s
+
+
+def log_to_numpy(buf, n: int) -> np.ndarray:
+    """Device event-log buffer (uint8 [n, 40]) to a structured numpy array."""
+    raw = buf[:n].cpu().numpy().reshape(-1)
+    return raw.view(EVENT_DTYPE).copy()

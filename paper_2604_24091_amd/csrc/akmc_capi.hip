@@ -1,0 +1,679 @@
+// C interface of the library (declared in include/akmc.h): argument
+// checks, workspace carving, launches, state read-back and replica
+// batches.  The library allocates no device memory; every device byte it
+// touches belongs to the caller's workspace or output buffers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "akmc_internal.hpp"
+
+using namespace akmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+akmc_status fail(akmc_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+akmc_status hip_fail(hipError_t e, const char *what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return AKMC_ERR_HIP;
+}
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t e__ = (expr);                            \
+    if (e__ != hipSuccess) return hip_fail(e__, #expr); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+constexpr uint64_t kFnvOffset = 0xcbf29ce484222325ull;
+constexpr int64_t kChunkEvents = int64_t(1) << 22;
+
+akmc_status check_params(const akmc_params *p) {
+  if (!p) return fail(AKMC_ERR_INVALID, "params is NULL");
+  if (p->lx < 3 || p->ly < 3 || p->lz < 3 || p->lx > 1000 || p->ly > 1000 || p->lz > 1000)
+    return fail(AKMC_ERR_INVALID, "lattice edges must lie in [3, 1000] cells");
+  if (2.0 * p->lx * (double)p->ly * p->lz >= 2147483647.0)
+    return fail(AKMC_ERR_INVALID, "2*lx*ly*lz must stay below 2^31 sites");
+  const int S = p->n_species;
+  if (S < 2 || S > AKMC_MAX_SPECIES) return fail(AKMC_ERR_INVALID, "n_species must lie in [2, 8]");
+  for (int a = 0; a < S; ++a)
+    for (int b = 0; b < S; ++b) {
+      const double e1 = p->eps1[a * S + b], e2 = p->eps2[a * S + b];
+      if (!std::isfinite(e1) || !std::isfinite(e2))
+        return fail(AKMC_ERR_INVALID, "pair energies must be finite");
+      if (e1 != p->eps1[b * S + a] || e2 != p->eps2[b * S + a])
+        return fail(AKMC_ERR_INVALID, "pair energy tables must be symmetric");
+    }
+  for (int a = 0; a < S - 1; ++a)
+    if (!std::isfinite(p->e0[a])) return fail(AKMC_ERR_INVALID, "e0 must be finite");
+  if (!(p->nu > 0.0) || !std::isfinite(p->nu)) return fail(AKMC_ERR_INVALID, "nu must be > 0");
+  if (!(p->temperature > 0.0) || !std::isfinite(p->temperature))
+    return fail(AKMC_ERR_INVALID, "temperature must be > 0");
+  if (!(p->kb > 0.0) || !std::isfinite(p->kb)) return fail(AKMC_ERR_INVALID, "kb must be > 0");
+  if (p->precision != AKMC_FP64 && p->precision != AKMC_FP32)
+    return fail(AKMC_ERR_INVALID, "precision must be AKMC_FP64 or AKMC_FP32");
+  if (p->refresh != AKMC_REFRESH_LOCAL && p->refresh != AKMC_REFRESH_FULL)
+    return fail(AKMC_ERR_INVALID, "refresh must be LOCAL or FULL");
+  if (p->time_mode != AKMC_TIME_STOCHASTIC && p->time_mode != AKMC_TIME_MEAN)
+    return fail(AKMC_ERR_INVALID, "time_mode must be STOCHASTIC or MEAN");
+  if (p->barrier_model != AKMC_BARRIER_PAIR && p->barrier_model != AKMC_BARRIER_MLP)
+    return fail(AKMC_ERR_INVALID, "barrier_model must be PAIR or MLP");
+  if (p->event_counter0 < 0) return fail(AKMC_ERR_INVALID, "event_counter0 must be >= 0");
+  if (!std::isfinite(p->time0)) return fail(AKMC_ERR_INVALID, "time0 must be finite");
+  return AKMC_OK;
+}
+
+int64_t n_sites_of(const akmc_params *p) { return 2ll * p->lx * p->ly * p->lz; }
+
+// Device description of one lattice, computed on the host in binary64.
+LatDesc make_desc(const akmc_params *p, int nv) {
+  LatDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.lx = p->lx; d.ly = p->ly; d.lz = p->lz;
+  d.S = p->n_species;
+  d.nv = nv;
+  d.time_mode = p->time_mode;
+  d.ncell = (int64_t)p->lx * p->ly * p->lz;
+  d.seed = p->seed;
+  d.stream = p->stream_id;
+  const int S = p->n_species, V = S - 1;
+  for (int A = 0; A < S; ++A)
+    for (int s = 0; s < S; ++s) {
+      const double d1 = p->eps1[A * S + s] - p->eps1[V * S + s];
+      const double d2 = p->eps2[A * S + s] - p->eps2[V * S + s];
+      d.D1[A * S + s] = d1;
+      d.D2[A * S + s] = d2;
+      d.D1f[A * S + s] = (float)d1;
+      d.D2f[A * S + s] = (float)d2;
+    }
+  for (int A = 0; A < S; ++A)
+    for (int s = 0; s < S; ++s) {
+      const double s1 = d.D1[A * S + s] - d.D1[A * S + 0];
+      const double s2 = d.D2[A * S + s] - d.D2[A * S + 0];
+      const double kk = d.D1[A * S + s] - d.D1[A * S + A];
+      d.Ds1[A * S + s] = s1; d.Ds2[A * S + s] = s2; d.K[A * S + s] = kk;
+      d.Ds1f[A * S + s] = (float)s1; d.Ds2f[A * S + s] = (float)s2; d.Kf[A * S + s] = (float)kk;
+    }
+  for (int a = 0; a < S - 1; ++a) {
+    d.e0[a] = p->e0[a];
+    d.e0f[a] = (float)p->e0[a];
+  }
+  d.nu = p->nu;
+  d.kT = p->kb * p->temperature;
+  d.nuf = (float)d.nu;
+  d.kTf = (float)d.kT;
+  d.beta = 1.0 / d.kT;
+  d.betaf = (float)d.beta;
+  return d;
+}
+
+struct WsLayout {
+  size_t desc, state, order, queue, slots, scratch, occ, total;
+};
+
+WsLayout ws_layout(int64_t nsites, int nv) {
+  WsLayout w;
+  size_t o = 0;
+  w.desc = o;    o += up(sizeof(LatDesc));
+  w.state = o;   o += up(sizeof(LatState));
+  w.order = o;   o += up(sizeof(int32_t));
+  w.queue = o;   o += up(sizeof(int32_t));
+  w.slots = o;   o += up(sizeof(int32_t) * (size_t)std::max(nv, 1));
+  w.scratch = o; o += up(sizeof(double) * 16 * (size_t)std::max(nv, 1));
+  w.occ = o;     o += up((size_t)nsites);
+  w.total = o;
+  return w;
+}
+
+bool aligned(const void *p) { return ((uintptr_t)p & (kAlign - 1)) == 0; }
+
+// Vacancy slots of a host occupancy: the given slot list (checked to be
+// exactly the set of vacancy sites) or all vacancy sites in ascending order.
+akmc_status build_slots(const akmc_params *p, const uint8_t *occ, const int32_t *given,
+                        std::vector<int32_t> &slots) {
+  const int64_t N = n_sites_of(p);
+  const int S = p->n_species;
+  slots.clear();
+  for (int64_t i = 0; i < N; ++i) {
+    if (occ[i] >= S) return fail(AKMC_ERR_INVALID, "occupancy holds a code >= n_species");
+    if (occ[i] == S - 1) slots.push_back((int32_t)i);
+  }
+  if ((int)slots.size() > AKMC_MAX_VACANCIES)
+    return fail(AKMC_ERR_UNSUPPORTED, "more than AKMC_MAX_VACANCIES vacancies");
+  if (given) {
+    std::vector<int32_t> a(given, given + slots.size());
+    std::vector<int32_t> b = a;
+    std::sort(b.begin(), b.end());
+    if (b != slots) return fail(AKMC_ERR_INVALID, "slot list is not the set of vacancy sites");
+    slots = a;
+  }
+  return AKMC_OK;
+}
+
+}  // namespace
+
+struct akmc_lattice {
+  akmc_params p;
+  int nv;
+  int64_t nsites;
+  hipStream_t stream;
+  unsigned char *ws;
+  WsLayout lay;
+  LatDesc h_desc;
+  LatDesc *d_desc;
+  LatState *d_state;
+  int32_t *d_order, *d_queue, *d_slots;
+  double *d_scratch;
+  uint8_t *d_occ;
+};
+
+extern "C" {
+
+akmc_status akmc_workspace_bytes(const akmc_params *p, int32_t n_vac, size_t *bytes) {
+  akmc_status s = check_params(p);
+  if (s != AKMC_OK) return s;
+  if (!bytes) return fail(AKMC_ERR_INVALID, "bytes is NULL");
+  if (n_vac < 0 || n_vac > AKMC_MAX_VACANCIES)
+    return fail(AKMC_ERR_INVALID, "n_vac must lie in [0, AKMC_MAX_VACANCIES]");
+  *bytes = ws_layout(n_sites_of(p), n_vac).total;
+  return AKMC_OK;
+}
+
+akmc_status akmc_lattice_create(const akmc_params *p, const uint8_t *occ_host,
+                                const int32_t *slot_sites_host, void *d_ws, size_t ws_bytes,
+                                void *hip_stream, akmc_handle *out) {
+  akmc_status st = check_params(p);
+  if (st != AKMC_OK) return st;
+  if (!occ_host || !d_ws || !out) return fail(AKMC_ERR_INVALID, "NULL occupancy, workspace or out");
+  if (!aligned(d_ws)) return fail(AKMC_ERR_INVALID, "workspace must be 256-byte aligned");
+  if (p->barrier_model != AKMC_BARRIER_PAIR)
+    return fail(AKMC_ERR_UNSUPPORTED, "barrier_model MLP needs the surrogate entry points");
+  const int64_t N = n_sites_of(p);
+  std::vector<int32_t> slots;
+  st = build_slots(p, occ_host, slot_sites_host, slots);
+  if (st != AKMC_OK) return st;
+  const int nv = (int)slots.size();
+  const WsLayout lay = ws_layout(N, nv);
+  if (ws_bytes < lay.total) return fail(AKMC_ERR_WORKSPACE, "workspace smaller than akmc_workspace_bytes");
+
+  akmc_lattice *h = new (std::nothrow) akmc_lattice;
+  if (!h) return fail(AKMC_ERR_INVALID, "out of host memory");
+  h->p = *p;
+  h->nv = nv;
+  h->nsites = N;
+  h->stream = (hipStream_t)hip_stream;
+  h->ws = (unsigned char *)d_ws;
+  h->lay = lay;
+  h->h_desc = make_desc(p, nv);
+  h->d_desc = (LatDesc *)(h->ws + lay.desc);
+  h->d_state = (LatState *)(h->ws + lay.state);
+  h->d_order = (int32_t *)(h->ws + lay.order);
+  h->d_queue = (int32_t *)(h->ws + lay.queue);
+  h->d_slots = (int32_t *)(h->ws + lay.slots);
+  h->d_scratch = (double *)(h->ws + lay.scratch);
+  h->d_occ = h->ws + lay.occ;
+
+  LatState s0;
+  std::memset(&s0, 0, sizeof(s0));
+  s0.t = p->time0;
+  s0.n = p->event_counter0;
+  s0.digest = p->digest0 ? p->digest0 : kFnvOffset;
+  s0.frozen = 0;
+  const int32_t zero = 0;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(h->d_desc, &h->h_desc, sizeof(LatDesc), hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(h->d_state, &s0, sizeof(s0), hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(h->d_order, &zero, sizeof(zero), hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+      (nv > 0 && (e = hipMemcpyAsync(h->d_slots, slots.data(), sizeof(int32_t) * nv,
+                                     hipMemcpyHostToDevice, h->stream)) != hipSuccess) ||
+      (e = hipMemcpyAsync(h->d_occ, occ_host, (size_t)N, hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(h->stream)) != hipSuccess) {
+    delete h;
+    return hip_fail(e, "lattice_create copies");
+  }
+  *out = h;
+  return AKMC_OK;
+}
+
+akmc_status akmc_rates_eval(akmc_handle h, int32_t mode, const int32_t *d_sites, int64_t n_sites,
+                            void *d_rates_out, void *d_ea_out) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (!d_rates_out) return fail(AKMC_ERR_INVALID, "rates output is NULL");
+  hipError_t e;
+  switch (mode) {
+    case AKMC_RATES_VACANCIES:
+      e = launch_rates_sites(h->d_desc, h->h_desc, h->d_occ, h->d_slots, h->nv, h->p.precision,
+                             d_rates_out, d_ea_out, h->stream);
+      break;
+    case AKMC_RATES_SITES:
+      if (n_sites < 0) return fail(AKMC_ERR_INVALID, "n_sites must be >= 0");
+      if (n_sites > 0 && !d_sites) return fail(AKMC_ERR_INVALID, "site list is NULL");
+      e = launch_rates_sites(h->d_desc, h->h_desc, h->d_occ, d_sites, n_sites, h->p.precision,
+                             d_rates_out, d_ea_out, h->stream);
+      break;
+    case AKMC_RATES_ALL_SITES:
+      e = launch_rates_all(h->d_desc, h->h_desc, h->d_occ, h->p.precision, d_rates_out, d_ea_out,
+                           h->stream);
+      break;
+    default:
+      return fail(AKMC_ERR_INVALID, "unknown rates_eval mode");
+  }
+  if (e != hipSuccess) return hip_fail(e, "rates_eval launch");
+  return AKMC_OK;
+}
+
+akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (n_events < 0) return fail(AKMC_ERR_INVALID, "n_events must be >= 0");
+  if (n_events == 0) return AKMC_OK;
+  if (h->nv == 0) return fail(AKMC_ERR_FROZEN, "lattice has no vacancies");
+  LoopArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.descs = h->d_desc;
+  a.states = h->d_state;
+  a.occ = h->d_occ;
+  a.slots = h->d_slots;
+  a.order = h->d_order;
+  a.queue = h->d_queue;
+  a.n_lat = 1;
+  a.nv_max = h->nv;
+  Schedule s{64, 1, 1};
+  for (int64_t done = 0; done < n_events; done += kChunkEvents) {
+    const int64_t n = std::min(kChunkEvents, n_events - done);
+    a.n_events = n;
+    a.log = d_log ? d_log + done : nullptr;
+    a.log_stride = n;
+    hipError_t e = launch_event_loop(a, h->p.precision, h->p.refresh == AKMC_REFRESH_FULL, s, h->stream);
+    if (e != hipSuccess) return hip_fail(e, "kmc_step launch");
+  }
+  return AKMC_OK;
+}
+
+static akmc_status read_state(hipStream_t stream, const LatDesc *d_desc, const LatDesc &hd,
+                              const LatState *d_state, const uint8_t *d_occ, const int32_t *d_slots,
+                              double *d_scratch, int nv, int64_t nsites, int precision,
+                              uint8_t *occ_host, int32_t *slots_host, akmc_summary *out) {
+  HIP_TRY(hipStreamSynchronize(stream));
+  LatState s;
+  HIP_TRY(hipMemcpy(&s, d_state, sizeof(s), hipMemcpyDeviceToHost));
+  if (slots_host && nv > 0)
+    HIP_TRY(hipMemcpy(slots_host, d_slots, sizeof(int32_t) * nv, hipMemcpyDeviceToHost));
+  std::vector<uint8_t> tmp;
+  const uint8_t *occ = occ_host;
+  if (out && !occ_host) {
+    tmp.resize((size_t)nsites);
+    occ = tmp.data();
+  }
+  if (occ) HIP_TRY(hipMemcpy((void *)occ, d_occ, (size_t)nsites, hipMemcpyDeviceToHost));
+  if (!out) return AKMC_OK;
+  std::memset(out, 0, sizeof(*out));
+  out->t = s.t;
+  out->n_events = s.n;
+  out->gamma_tot = s.gamma_tot;
+  out->digest = s.digest;
+  out->n_ood = s.n_ood;
+  out->n_vacancies = nv;
+  out->frozen = s.frozen;
+  for (int64_t i = 0; i < nsites; ++i) out->species_count[occ[i] & 7] += 1;
+  if (nv > 0) {
+    // Barriers of the current candidates, for the negative-barrier count.
+    hipError_t e = launch_rates_sites(d_desc, hd, d_occ, d_slots, nv, precision,
+                                      (void *)(d_scratch + 8 * nv), (void *)d_scratch, stream);
+    if (e != hipSuccess) return hip_fail(e, "state_read barriers");
+    HIP_TRY(hipStreamSynchronize(stream));
+    std::vector<double> ea64((size_t)nv * 8);
+    if (precision == AKMC_FP32) {
+      std::vector<float> ea32((size_t)nv * 8);
+      HIP_TRY(hipMemcpy(ea32.data(), d_scratch, sizeof(float) * 8 * nv, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < ea32.size(); ++i) ea64[i] = ea32[i];
+    } else {
+      HIP_TRY(hipMemcpy(ea64.data(), d_scratch, sizeof(double) * 8 * nv, hipMemcpyDeviceToHost));
+    }
+    for (double v : ea64)
+      if (v < 0.0) out->n_neg_barrier += 1;
+  }
+  return AKMC_OK;
+}
+
+akmc_status akmc_state_read(akmc_handle h, uint8_t *occ_host, int32_t *slot_sites_host,
+                            akmc_summary *out) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  return read_state(h->stream, h->d_desc, h->h_desc, h->d_state, h->d_occ, h->d_slots,
+                    h->d_scratch, h->nv, h->nsites, h->p.precision, occ_host, slot_sites_host, out);
+}
+
+akmc_status akmc_lattice_destroy(akmc_handle h) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  delete h;
+  return AKMC_OK;
+}
+
+const char *akmc_status_string(akmc_status s) {
+  switch (s) {
+    case AKMC_OK: return "ok";
+    case AKMC_ERR_INVALID: return "invalid argument";
+    case AKMC_ERR_WORKSPACE: return "workspace too small";
+    case AKMC_ERR_HIP: return "HIP runtime error";
+    case AKMC_ERR_FROZEN: return "frozen: total rate is zero";
+    case AKMC_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char *akmc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------- batches
+
+struct akmc_batch_s {
+  int n_rep;
+  int precision, refresh_full;
+  hipStream_t stream;
+  unsigned char *ws;
+  std::vector<akmc_params> params;
+  std::vector<LatDesc> h_descs;
+  std::vector<int> nv;
+  std::vector<int64_t> nsites;
+  int nv_max;
+  LatDesc *d_descs;
+  LatState *d_states;
+  int32_t *d_order, *d_queue, *d_slots;
+  double *d_scratch;
+  uint8_t *d_occ;
+  akmc_schedule sched;
+  hipStream_t cap_stream = nullptr;   // capture-only stream (the legacy stream cannot capture)
+  std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t descs, states, order, queue, slots, scratch, occ, total;
+  std::vector<int64_t> occ_off, slot_off;
+};
+
+BatchLayout batch_layout(int n_rep, const akmc_params *p, const int32_t *n_vac) {
+  BatchLayout b;
+  size_t o = 0;
+  b.descs = o;  o += up(sizeof(LatDesc) * (size_t)n_rep);
+  b.states = o; o += up(sizeof(LatState) * (size_t)n_rep);
+  b.order = o;  o += up(sizeof(int32_t) * (size_t)n_rep);
+  b.queue = o;  o += up(sizeof(int32_t));
+  int64_t ns = 0, nvmax = 1;
+  for (int r = 0; r < n_rep; ++r) {
+    b.slot_off.push_back(ns);
+    ns += n_vac[r];
+    nvmax = std::max<int64_t>(nvmax, n_vac[r]);
+  }
+  b.slots = o;   o += up(sizeof(int32_t) * (size_t)std::max<int64_t>(ns, 1));
+  b.scratch = o; o += up(sizeof(double) * 16 * (size_t)nvmax);
+  b.occ = o;
+  int64_t oo = 0;
+  for (int r = 0; r < n_rep; ++r) {
+    b.occ_off.push_back(oo);
+    oo += (int64_t)up((size_t)n_sites_of(&p[r]));
+  }
+  o += (size_t)oo;
+  b.total = o;
+  return b;
+}
+
+akmc_status check_schedule(const akmc_schedule *s) {
+  if (!s) return fail(AKMC_ERR_INVALID, "schedule is NULL");
+  if (s->group_lanes != 8 && s->group_lanes != 16 && s->group_lanes != 32 && s->group_lanes != 64)
+    return fail(AKMC_ERR_INVALID, "group_lanes must be 8, 16, 32 or 64");
+  if (s->waves_per_block != 1 && s->waves_per_block != 2 && s->waves_per_block != 4)
+    return fail(AKMC_ERR_INVALID, "waves_per_block must be 1, 2 or 4");
+  if (s->blocks < 0) return fail(AKMC_ERR_INVALID, "blocks must be >= 0");
+  if (s->chunk_events <= 0) return fail(AKMC_ERR_INVALID, "chunk_events must be > 0");
+  return AKMC_OK;
+}
+
+LoopArgs batch_args(const akmc_batch_s *b, int64_t n) {
+  LoopArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.descs = b->d_descs;
+  a.states = b->d_states;
+  a.occ = b->d_occ;
+  a.slots = b->d_slots;
+  a.order = b->d_order;
+  a.queue = b->d_queue;
+  a.n_lat = b->n_rep;
+  a.nv_max = b->nv_max;
+  a.n_events = n;
+  return a;
+}
+
+akmc_status batch_launch(akmc_batch_s *b, int64_t n, hipStream_t stream) {
+  const Schedule s{b->sched.group_lanes, b->sched.waves_per_block, b->sched.blocks};
+  hipError_t e = launch_event_loop(batch_args(b, n), b->precision, b->refresh_full, s, stream);
+  if (e != hipSuccess) return hip_fail(e, "batch launch");
+  return AKMC_OK;
+}
+
+// One chunk as a graph: [queue reset, persistent loop], captured once per
+// (chunk, schedule) on the library's capture stream and replayed on the
+// caller's stream.
+akmc_status batch_graph_launch(akmc_batch_s *b, int64_t n) {
+  std::vector<int64_t> key{n, b->sched.group_lanes, b->sched.waves_per_block, b->sched.blocks};
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    akmc_status st = batch_launch(b, n, b->cap_stream);
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+    if (st != AKMC_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    it = b->graphs.emplace(key, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, b->stream));
+  return AKMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+akmc_status akmc_batch_workspace_bytes(int32_t n_rep, const akmc_params *p, const int32_t *n_vac,
+                                       size_t *bytes) {
+  if (n_rep <= 0 || !p || !n_vac || !bytes) return fail(AKMC_ERR_INVALID, "bad batch arguments");
+  for (int r = 0; r < n_rep; ++r) {
+    akmc_status s = check_params(&p[r]);
+    if (s != AKMC_OK) return s;
+    if (n_vac[r] < 0 || n_vac[r] > AKMC_MAX_VACANCIES)
+      return fail(AKMC_ERR_INVALID, "n_vac must lie in [0, AKMC_MAX_VACANCIES]");
+  }
+  *bytes = batch_layout(n_rep, p, n_vac).total;
+  return AKMC_OK;
+}
+
+akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p, const uint8_t *const *occ_host,
+                              const int32_t *const *slot_sites_host, void *d_ws, size_t ws_bytes,
+                              void *hip_stream, akmc_batch *out) {
+  if (n_rep <= 0 || !p || !occ_host || !d_ws || !out)
+    return fail(AKMC_ERR_INVALID, "bad batch arguments");
+  if (!aligned(d_ws)) return fail(AKMC_ERR_INVALID, "workspace must be 256-byte aligned");
+  std::vector<int32_t> nv(n_rep);
+  std::vector<std::vector<int32_t>> slots(n_rep);
+  for (int r = 0; r < n_rep; ++r) {
+    akmc_status s = check_params(&p[r]);
+    if (s != AKMC_OK) return s;
+    if (!occ_host[r]) return fail(AKMC_ERR_INVALID, "replica occupancy is NULL");
+    if (p[r].precision != p[0].precision || p[r].refresh != p[0].refresh)
+      return fail(AKMC_ERR_INVALID, "precision and refresh must agree across replicas");
+    if (p[r].barrier_model != AKMC_BARRIER_PAIR)
+      return fail(AKMC_ERR_UNSUPPORTED, "batches use the pair barrier model");
+    s = build_slots(&p[r], occ_host[r], slot_sites_host ? slot_sites_host[r] : nullptr, slots[r]);
+    if (s != AKMC_OK) return s;
+    nv[r] = (int32_t)slots[r].size();
+  }
+  const BatchLayout lay = batch_layout(n_rep, p, nv.data());
+  if (ws_bytes < lay.total) return fail(AKMC_ERR_WORKSPACE, "workspace smaller than akmc_batch_workspace_bytes");
+
+  akmc_batch_s *b = new (std::nothrow) akmc_batch_s;
+  if (!b) return fail(AKMC_ERR_INVALID, "out of host memory");
+  b->n_rep = n_rep;
+  b->precision = p[0].precision;
+  b->refresh_full = p[0].refresh == AKMC_REFRESH_FULL;
+  b->stream = (hipStream_t)hip_stream;
+  b->ws = (unsigned char *)d_ws;
+  b->params.assign(p, p + n_rep);
+  b->nv.assign(nv.begin(), nv.end());
+  b->nv_max = 1;
+  for (int r = 0; r < n_rep; ++r) b->nv_max = std::max(b->nv_max, nv[r]);
+  b->d_descs = (LatDesc *)(b->ws + lay.descs);
+  b->d_states = (LatState *)(b->ws + lay.states);
+  b->d_order = (int32_t *)(b->ws + lay.order);
+  b->d_queue = (int32_t *)(b->ws + lay.queue);
+  b->d_slots = (int32_t *)(b->ws + lay.slots);
+  b->d_scratch = (double *)(b->ws + lay.scratch);
+  b->d_occ = b->ws + lay.occ;
+  b->sched = akmc_schedule{8, 1, 0, 0, 1 << 30};
+
+  std::vector<LatState> states(n_rep);
+  std::vector<double> weight(n_rep);
+  std::vector<int32_t> order(n_rep);
+  for (int r = 0; r < n_rep; ++r) {
+    LatDesc d = make_desc(&p[r], nv[r]);
+    d.occ_off = lay.occ_off[r];
+    d.slot_off = lay.slot_off[r];
+    b->h_descs.push_back(d);
+    b->nsites.push_back(n_sites_of(&p[r]));
+    LatState s;
+    std::memset(&s, 0, sizeof(s));
+    s.t = p[r].time0;
+    s.n = p[r].event_counter0;
+    s.digest = p[r].digest0 ? p[r].digest0 : kFnvOffset;
+    s.frozen = nv[r] == 0 ? 1 : 0;
+    states[r] = s;
+    // Work proxy of Eq. 10: event multiplicity times the Arrhenius factor of
+    // the matrix barrier at the replica's temperature.
+    weight[r] = (double)nv[r] * 8.0 * std::exp(-p[r].e0[0] / (p[r].kb * p[r].temperature));
+    order[r] = r;
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return weight[x] > weight[y]; });
+  hipError_t e = hipSuccess;
+  const hipStream_t st = b->stream;
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_descs, b->h_descs.data(), sizeof(LatDesc) * n_rep, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_states, states.data(), sizeof(LatState) * n_rep, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_order, order.data(), sizeof(int32_t) * n_rep, hipMemcpyHostToDevice, st);
+  for (int r = 0; r < n_rep && e == hipSuccess; ++r) {
+    if (nv[r] > 0)
+      e = hipMemcpyAsync(b->d_slots + lay.slot_off[r], slots[r].data(), sizeof(int32_t) * nv[r],
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->d_occ + lay.occ_off[r], occ_host[r], (size_t)b->nsites[r],
+                         hipMemcpyHostToDevice, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    delete b;
+    return hip_fail(e, "batch_create copies");
+  }
+  *out = b;
+  return AKMC_OK;
+}
+
+akmc_status akmc_batch_set_schedule(akmc_batch b, const akmc_schedule *s) {
+  if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
+  akmc_status st = check_schedule(s);
+  if (st != AKMC_OK) return st;
+  b->sched = *s;
+  return AKMC_OK;
+}
+
+akmc_status akmc_batch_step(akmc_batch b, int64_t n_events_per_replica) {
+  if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
+  if (n_events_per_replica < 0) return fail(AKMC_ERR_INVALID, "n_events must be >= 0");
+  int64_t done = 0;
+  const int64_t chunk = std::min<int64_t>(b->sched.chunk_events, kChunkEvents);
+  while (done < n_events_per_replica) {
+    const int64_t n = std::min(chunk, n_events_per_replica - done);
+    akmc_status st = b->sched.use_graph ? batch_graph_launch(b, n) : batch_launch(b, n, b->stream);
+    if (st != AKMC_OK) return st;
+    done += n;
+  }
+  return AKMC_OK;
+}
+
+akmc_status akmc_batch_autotune(akmc_batch b, int64_t trial_events, akmc_schedule *chosen) {
+  if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
+  if (trial_events <= 0) return fail(AKMC_ERR_INVALID, "trial_events must be > 0");
+  const int lanes[4] = {8, 16, 32, 64};
+  const int waves[2] = {1, 2};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const akmc_schedule keep = b->sched;
+  akmc_schedule best = keep;
+  float best_ms = 1e30f;
+  for (int G : lanes)
+    for (int W : waves) {
+      akmc_schedule s = keep;
+      s.group_lanes = G;
+      s.waves_per_block = W;
+      s.blocks = 0;
+      s.use_graph = 0;
+      s.chunk_events = trial_events;
+      b->sched = s;
+      HIP_TRY(hipEventRecord(e0, b->stream));
+      akmc_status st = akmc_batch_step(b, trial_events);
+      if (st != AKMC_OK) { b->sched = keep; return st; }
+      HIP_TRY(hipEventRecord(e1, b->stream));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) { best_ms = ms; best = s; }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  best.use_graph = keep.use_graph;
+  best.chunk_events = keep.chunk_events;
+  b->sched = best;
+  if (chosen) *chosen = best;
+  return AKMC_OK;
+}
+
+akmc_status akmc_batch_state_read(akmc_batch b, int32_t r, uint8_t *occ_host,
+                                  int32_t *slot_sites_host, akmc_summary *out) {
+  if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
+  if (r < 0 || r >= b->n_rep) return fail(AKMC_ERR_INVALID, "replica index out of range");
+  const LatDesc &d = b->h_descs[r];
+  return read_state(b->stream, b->d_descs + r, d, b->d_states + r, b->d_occ + d.occ_off,
+                    b->d_slots + d.slot_off, b->d_scratch, b->nv[r], b->nsites[r], b->precision,
+                    occ_host, slot_sites_host, out);
+}
+
+akmc_status akmc_batch_destroy(akmc_batch b) {
+  if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
+  for (auto &kv : b->graphs) hipGraphExecDestroy(kv.second);
+  if (b->cap_stream) hipStreamDestroy(b->cap_stream);
+  delete b;
+  return AKMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,138 @@
+// Device helpers of the vacancy-jump path: lattice positions, the Philox
+// stream, the event digest and the per-candidate energy change.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "akmc_internal.hpp"
+
+namespace akmc {
+
+// ------------------------------------------------------------ positions
+// A site is addressed by its position in units of a/2: X = 2x + b etc., in
+// a periodic box of 2*lx x 2*ly x 2*lz.  The corner (b = 0) has even
+// coordinates, the body centre (b = 1) odd ones.  First neighbours are the
+// 8 offsets (+-1, +-1, +-1), second neighbours the 6 offsets +-2 along one
+// axis, in the order (+x, -x, +y, -y, +z, -z).
+
+struct Geo {
+  int lx, ly, lz;
+  int X2, Y2, Z2;   // box edges in a/2 units
+  int ncell;
+};
+
+__device__ __forceinline__ Geo make_geo(int lx, int ly, int lz) {
+  Geo g;
+  g.lx = lx; g.ly = ly; g.lz = lz;
+  g.X2 = 2 * lx; g.Y2 = 2 * ly; g.Z2 = 2 * lz;
+  g.ncell = lx * ly * lz;
+  return g;
+}
+
+__device__ __forceinline__ int wrapc(int v, int L2) {
+  v = v < 0 ? v + L2 : v;
+  return v >= L2 ? v - L2 : v;
+}
+
+__device__ __forceinline__ int site_of(const Geo &g, int X, int Y, int Z) {
+  return (X & 1) * g.ncell + ((Z >> 1) * g.ly + (Y >> 1)) * g.lx + (X >> 1);
+}
+
+__device__ __forceinline__ void pos_of(const Geo &g, int site, int &X, int &Y, int &Z) {
+  int b = site >= g.ncell ? 1 : 0;
+  int r = site - b * g.ncell;
+  int x = r % g.lx;
+  r /= g.lx;
+  int y = r % g.ly;
+  int z = r / g.ly;
+  X = 2 * x + b;
+  Y = 2 * y + b;
+  Z = 2 * z + b;
+}
+
+// Packed position (11 bits per axis; edges are limited to 1000 cells).
+__device__ __forceinline__ int pack_pos(int X, int Y, int Z) { return X | (Y << 11) | (Z << 22); }
+__device__ __forceinline__ int pos_x(int p) { return p & 2047; }
+__device__ __forceinline__ int pos_y(int p) { return (p >> 11) & 2047; }
+__device__ __forceinline__ int pos_z(int p) { return (p >> 22) & 2047; }
+
+__device__ __forceinline__ int dir_sx(int k) { return ((k >> 2) & 1) ? 1 : -1; }
+__device__ __forceinline__ int dir_sy(int k) { return ((k >> 1) & 1) ? 1 : -1; }
+__device__ __forceinline__ int dir_sz(int k) { return (k & 1) ? 1 : -1; }
+
+// -------------------------------------------------------------- Philox
+// Philox4x64 with 10 rounds (Salmon, Moraes, Dror, Shaw, SC'11):
+// multipliers 0xD2E7470EE14C6C93, 0xCA5A826395121157, key increments the
+// golden-ratio and sqrt(3)-1 Weyl constants.
+__device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                              uint64_t k0, uint64_t k1, uint64_t out[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+    uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    k0 += W0; k1 += W1;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Event n's uniforms: u1 in [0,1) from word 0, u2 in (0,1] from word 1.
+__device__ __forceinline__ void event_uniforms(uint64_t seed, uint64_t stream, int64_t n,
+                                               double &u1, double &u2) {
+  uint64_t x[4];
+  philox4x64_10((uint64_t)n, 0, 0, 0, seed, stream, x);
+  const double two_m53 = 1.1102230246251565404e-16;  // 2^-53
+  u1 = (double)(x[0] >> 11) * two_m53;
+  u2 = (double)((x[1] >> 11) + 1) * two_m53;
+}
+
+// -------------------------------------------------------------- digest
+// FNV-1a 64 over the 16 little-endian bytes of (n, from, to).
+__device__ __forceinline__ uint64_t fnv_event(uint64_t h, int64_t n, int32_t from, int32_t to) {
+  const uint64_t P = 0x100000001b3ull;
+  uint64_t un = (uint64_t)n;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) { h ^= (un >> (8 * a)) & 0xff; h *= P; }
+  uint32_t uf = (uint32_t)from, ut = (uint32_t)to;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) { h ^= (uf >> (8 * a)) & 0xff; h *= P; }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) { h ^= (ut >> (8 * a)) & 0xff; h *= P; }
+  return h;
+}
+
+// ------------------------------------------------- candidate energetics
+// Species counts are kept as 8 nibbles of a 32-bit word (one per species
+// code); a shell has at most 8 members, so no nibble overflows.
+__device__ __forceinline__ uint32_t onehot(int s) { return 1u << (4 * s); }
+__device__ __forceinline__ int nib(uint32_t c, int s) { return (int)((c >> (4 * s)) & 15u); }
+
+// Energy change from the bond counts, as one fused multiply-add chain over
+// species codes, shell 1 first:  dE = sum_s dn1[s] D1[A][s] + dn2[s] D2[A][s]
+// with dn1 = c1i - c1j (first shells of i without j and of j without i)
+// and dn2 = c2i - c2j (second shells).  The counts are exact integers, so
+// any way of gathering them gives the same bits.
+template <class Real>
+__device__ __forceinline__ Real delta_e_counts(uint32_t c1i, uint32_t c1j, uint32_t c2i,
+                                               uint32_t c2j, const Real *D1row,
+                                               const Real *D2row, int S) {
+  Real acc = Real(0);
+  for (int s = 0; s < S; ++s) acc = fma((Real)(nib(c1i, s) - nib(c1j, s)), D1row[s], acc);
+  for (int s = 0; s < S; ++s) acc = fma((Real)(nib(c2i, s) - nib(c2j, s)), D2row[s], acc);
+  return acc;
+}
+
+__device__ __forceinline__ double rate_from_barrier(double ea, double nu, double kT) {
+  double x = -(ea / kT);
+  return nu * exp(x);
+}
+__device__ __forceinline__ float rate_from_barrier(float ea, float nu, float kT) {
+  float x = -(ea / kT);
+  return nu * expf(x);
+}
+
+}  // namespace akmc

@@ -1,0 +1,131 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/akmc.h"
+
+namespace akmc {
+
+// Read-only description of one lattice (one replica), resident in device
+// memory.  Tables hold D_k[A][s] = eps_k[A][s] - eps_k[V][s], rounded once
+// from the binary64 difference.
+struct LatDesc {
+  int32_t lx, ly, lz, S;
+  int32_t nv;                 // vacancy slots
+  int32_t time_mode;
+  int64_t ncell;              // lx*ly*lz
+  int64_t occ_off;            // byte offset of the occupancy in the occupancy arena
+  int64_t slot_off;           // element offset in the slot arena
+  uint64_t seed, stream;
+  double D1[64], D2[64];      // row A: D_k[A][0..S-1]
+  double e0[8];
+  double nu, kT;              // kT = kb*T in binary64
+  float D1f[64], D2f[64];
+  float e0f[8];
+  float nuf, kTf;
+  // Tables of the bulk sweep (relative to the all-Fe environment):
+  //   Ds_k[A][s] = D_k[A][s] - D_k[A][0],  K[A][s] = D1[A][s] - D1[A][A].
+  double Ds1[64], Ds2[64], K[64];
+  float Ds1f[64], Ds2f[64], Kf[64];
+  double beta;                // 1/kT
+  float betaf;
+  int32_t pad_[1];
+};
+
+// Mutable per-lattice state.
+struct LatState {
+  double t;
+  int64_t n;                  // next global event index
+  uint64_t digest;
+  double gamma_tot;
+  int64_t n_ood;
+  int32_t frozen;
+  int32_t pad_;
+};
+
+// Event-loop launch description.
+struct LoopArgs {
+  const LatDesc *descs;
+  LatState *states;
+  uint8_t *occ;               // occupancy arena
+  int32_t *slots;             // slot arena (site of each slot)
+  akmc_event *log;            // NULL or [n_lat][log_stride]
+  int64_t log_stride;
+  const int32_t *order;       // processing order of lattices (heaviest first)
+  int32_t *queue;             // work-queue counter (reset by the launcher)
+  int32_t n_lat;
+  int32_t nv_max;             // LDS sizing
+  int32_t refresh_full;       // 1: refresh every slot after every event
+  int64_t n_events;           // per lattice
+};
+
+// LDS carve-up of one lattice group in the event loop.  Every array is
+// sized for nv_max slots; the tree levels hold partial sums of groups of 8
+// children: level 1 over slot totals, level l+1 over the last partial of
+// each level-l group, until one group of at most 8 nodes remains.
+constexpr int kBoxBytes = 352;   // 7x7x7 footprint box, padded to 16
+constexpr int kMaxLevels = 4;
+
+struct GroupLayout {
+  int nv_max, G, fp32, nlev_max;
+  int qlen[kMaxLevels + 1];       // elements of level l (1-based)
+  int qoff[kMaxLevels + 1];       // element offset of level l in the Q region
+  int off_part, off_q, off_pos, off_aff, off_la, off_lb, off_spec, off_box, off_tab, off_rng;
+  int bytes;
+};
+
+__host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
+
+__host__ __device__ inline GroupLayout make_layout(int nv_max, int G, int fp32) {
+  GroupLayout L{};
+  L.nv_max = nv_max;
+  L.G = G;
+  L.fp32 = fp32;
+  int n = nv_max, lev = 1, qtot = 0;
+  for (;;) {
+    L.qlen[lev] = n;
+    L.qoff[lev] = qtot;
+    qtot += n;
+    if (n <= 8 || lev == kMaxLevels) break;
+    n = (n + 7) / 8;
+    ++lev;
+  }
+  L.nlev_max = lev;
+  const int real = fp32 ? 4 : 8;
+  int o = 0;
+  L.off_part = o; o = align16(o + nv_max * 8 * 8);
+  L.off_q = o;    o = align16(o + qtot * 8);
+  L.off_pos = o;  o = align16(o + nv_max * 4);
+  L.off_aff = o;  o = align16(o + nv_max * 4);
+  L.off_la = o;   o = align16(o + nv_max * 4);
+  L.off_lb = o;   o = align16(o + nv_max * 4);
+  L.off_spec = o; o = align16(o + nv_max * 8);
+  L.off_box = o;  o = align16(o + (G / 8) * kBoxBytes);
+  L.off_tab = o;  o = align16(o + (64 + 64 + 8) * real);
+  L.off_rng = o;  o = align16(o + 2 * G * 8);
+  L.bytes = o;
+  return L;
+}
+
+struct Schedule {
+  int group_lanes;
+  int waves_per_block;
+  int blocks;
+};
+
+// Launchers (return hipError_t).
+hipError_t launch_event_loop(const LoopArgs &a, int precision, int refresh_full,
+                             const Schedule &s, hipStream_t stream);
+size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision);
+hipError_t launch_queue_reset(int32_t *queue, hipStream_t stream);
+
+hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h_desc, const uint8_t *occ,
+                              const int32_t *sites, int64_t n_sites, int precision,
+                              void *rates, void *ea, hipStream_t stream);
+hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h_desc, const uint8_t *occ,
+                            int precision, void *rates, void *ea, hipStream_t stream);
+
+}  // namespace akmc

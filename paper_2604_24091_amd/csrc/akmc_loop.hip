@@ -1,0 +1,571 @@
+// Persistent residence-time event loop.
+//
+// One group of G lanes (G = 8, 16, 32 or 64, always inside one wavefront)
+// owns one lattice for a whole launch and runs its events back to back
+// with no host round trip.  Groups pull lattices from a device work queue
+// in a given order (heaviest first for replica ensembles), so a launch can
+// serve one lattice or a voxel ensemble of uneven replicas.
+//
+// Per event (all of it group-local, synchronised at wavefront level):
+//   1. uniforms of event n from Philox4x64-10 (computed G events ahead,
+//      one per lane, together with -ln u2);
+//   2. selection: target = u1 * Gamma_tot, descended through a tree of
+//      binary64 partial sums held in LDS (fan-out 8 at every level: 8
+//      directions per slot, then groups of 8 slots, ...).  Every node is
+//      the left-to-right sum of its children, so the sums do not depend on
+//      G, on which slots were refreshed, or on the launch split;
+//   3. dt = -ln(u2)/Gamma_tot, t += dt, digest update;
+//   4. swap of atom and vacancy in the global occupancy;
+//   5. local refresh: every slot whose vacancy lies within 4 half-lattice
+//      units (Chebyshev, minimum image) of the old vacancy site is
+//      re-evaluated; that covers every slot whose 58-site bond footprint
+//      contains one of the two changed sites.  Each refreshed vacancy's
+//      footprint is gathered once into a 7x7x7 LDS box and its 8
+//      candidates read their bond counts from there;
+//   6. the changed tree paths are re-summed.
+#include <hip/hip_runtime.h>
+
+#include "akmc_device.hpp"
+#include "akmc_internal.hpp"
+
+namespace akmc {
+
+// The 58 sites (offsets in a/2 units) that the bonds of any of the 8 jumps
+// of a vacancy touch: the 8 first and 6 second neighbours, the 20 offsets
+// with all components in {0, +-2} and two or three of them non-zero (first
+// shells of the targets), and the 24 offsets with one component +-3 and the
+// others +-1 (second shells of the targets).
+struct FootTab {
+  int8_t d[64][3];
+  int n;
+};
+
+constexpr int iabs_c(int v) { return v < 0 ? -v : v; }
+
+constexpr FootTab make_foot() {
+  FootTab t{};
+  int n = 0;
+  for (int dz = -3; dz <= 3; ++dz)
+    for (int dy = -3; dy <= 3; ++dy)
+      for (int dx = -3; dx <= 3; ++dx) {
+        const int ax = iabs_c(dx), ay = iabs_c(dy), az = iabs_c(dz);
+        const bool odd = (ax & 1) && (ay & 1) && (az & 1);
+        const int threes = (ax == 3) + (ay == 3) + (az == 3);
+        const bool even = !(ax & 1) && !(ay & 1) && !(az & 1) && ax <= 2 && ay <= 2 && az <= 2 &&
+                          (ax + ay + az) > 0;
+        if ((odd && threes <= 1) || even) {
+          t.d[n][0] = (int8_t)dx;
+          t.d[n][1] = (int8_t)dy;
+          t.d[n][2] = (int8_t)dz;
+          ++n;
+        }
+      }
+  t.n = n;
+  return t;
+}
+
+constexpr FootTab kFootHost = make_foot();
+static_assert(kFootHost.n == 58, "footprint of a vacancy has 58 sites");
+__constant__ FootTab kFoot = make_foot();
+
+constexpr int kFootN = 59;       // 58 gathered sites + the vacancy itself
+constexpr int kBoxC = 3 + 7 * 3 + 49 * 3;
+
+template <int G>
+struct Group {
+  int gw, gl, base;
+  __device__ __forceinline__ uint64_t ballot(bool p) const {
+    const uint64_t m = __ballot(p);
+    if (G == 64) return m;
+    return (m >> base) & ((1ull << (G & 63)) - 1ull);
+  }
+  __device__ __forceinline__ uint64_t lanes_below() const {
+    return gl == 0 ? 0ull : ((1ull << gl) - 1ull);
+  }
+  template <class T>
+  __device__ __forceinline__ T bcast(T v, int src) const {
+    return __shfl(v, base + src, 64);
+  }
+};
+
+// Orders LDS traffic of the wavefront (a group never spans wavefronts).
+__device__ __forceinline__ void gsync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class Real>
+struct Lds {
+  double *part;     // [nv][8] partial sums over directions, part[v][7] = slot total
+  double *q;        // tree levels
+  int *pos;         // packed vacancy positions
+  int *aff;         // refreshed slots, ascending
+  int *la, *lb;     // group lists of the tree update
+  uint8_t *spec;    // [nv][8] species of each candidate's target
+  uint8_t *box;     // (G/8) footprint boxes
+  Real *D1, *D2, *e0;
+  double *ru1, *rw; // uniforms u1 and -ln u2 of the next G events
+};
+
+template <class Real>
+__device__ __forceinline__ Lds<Real> carve(unsigned char *base, const GroupLayout &L) {
+  Lds<Real> s;
+  s.part = (double *)(base + L.off_part);
+  s.q = (double *)(base + L.off_q);
+  s.pos = (int *)(base + L.off_pos);
+  s.aff = (int *)(base + L.off_aff);
+  s.la = (int *)(base + L.off_la);
+  s.lb = (int *)(base + L.off_lb);
+  s.spec = base + L.off_spec;
+  s.box = base + L.off_box;
+  s.D1 = (Real *)(base + L.off_tab);
+  s.D2 = s.D1 + 64;
+  s.e0 = s.D2 + 64;
+  s.ru1 = (double *)(base + L.off_rng);
+  s.rw = s.ru1 + L.G;
+  return s;
+}
+
+// Rate of candidate k of the vacancy whose footprint sits in `box`.  Bond
+// counts as in the site-list kernel: N1(i) without j, N1(j) without i,
+// N2(i), N2(j).  Returns the rate widened to binary64 and the target species.
+template <class Real>
+__device__ __forceinline__ double eval_box(const uint8_t *box, int k, int S, const Real *D1,
+                                           const Real *D2, const Real *e0, Real nu, Real kT,
+                                           int &A_out) {
+  const int V = S - 1;
+  const int jb = kBoxC + dir_sx(k) + 7 * dir_sy(k) + 49 * dir_sz(k);
+  const int A = box[jb];
+  A_out = A;
+  if (A == V) return 0.0;
+  uint32_t c1i = 0, c1j = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int off = dir_sx(q) + 7 * dir_sy(q) + 49 * dir_sz(q);
+    c1i += onehot(box[kBoxC + off]);
+    c1j += onehot(box[jb + off]);
+  }
+  const uint32_t c2i = onehot(box[kBoxC + 2]) + onehot(box[kBoxC - 2]) + onehot(box[kBoxC + 14]) +
+                       onehot(box[kBoxC - 14]) + onehot(box[kBoxC + 98]) + onehot(box[kBoxC - 98]);
+  const uint32_t c2j = onehot(box[jb + 2]) + onehot(box[jb - 2]) + onehot(box[jb + 14]) +
+                       onehot(box[jb - 14]) + onehot(box[jb + 98]) + onehot(box[jb - 98]);
+  c1i -= onehot(A);
+  c1j -= onehot(box[kBoxC]);
+  const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, D1 + A * S, D2 + A * S, S);
+  const Real ea = e0[A] + Real(0.5) * de;
+  return (double)rate_from_barrier(ea, nu, kT);
+}
+
+template <int G, class Real>
+struct Runner {
+  LoopArgs a;
+  int qo1, qo2, qo3, qo4;   // level offsets in the tree region
+  Group<G> gp;
+  int foot[8];
+  Lds<Real> s;
+  Geo g;
+  int S, V, nv, nlev;
+  Real nu, kT;
+  uint8_t *occ;
+
+  __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
+                    const int (&foot_)[8], unsigned char *lds)
+      : a(a_), gp(gp_) {
+    s = carve<Real>(lds, L);
+    qo1 = L.qoff[1];
+    qo2 = L.qoff[2];
+    qo3 = L.qoff[3];
+    qo4 = L.qoff[4];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) foot[m] = foot_[m];
+  }
+
+  // Level l (1-based) of the tree: its nodes and their count.
+  __device__ __forceinline__ double *Q(int l) const {
+    return s.q + (l == 1 ? qo1 : l == 2 ? qo2 : l == 3 ? qo3 : qo4);
+  }
+  __device__ __forceinline__ int nl(int l) const {
+    const int sh = 3 * (l - 1);
+    return (nv + (1 << sh) - 1) >> sh;
+  }
+
+  __device__ double node_value(int l, int u) const {
+    if (l == 1) return s.part[u * 8 + 7];
+    const int cnt = min(8, nl(l - 1) - 8 * u);
+    return Q(l - 1)[8 * u + cnt - 1];
+  }
+
+  // Re-evaluates the slots aff[0..na).
+  __device__ void refresh(int na) {
+    constexpr int P = G / 8;
+    for (int p0 = 0; p0 < na; p0 += P) {
+      const int np = min(P, na - p0);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int f = foot[m];
+        if (f < 0) continue;
+        const int q = (f >> 18) & 63;
+        if (q >= np) continue;
+        const int bi = f & 511;
+        uint8_t val;
+        if (f & (1 << 24)) {
+          val = (uint8_t)V;
+        } else {
+          const int pp = s.pos[s.aff[p0 + q]];
+          const int X = wrapc(pos_x(pp) + ((f >> 9) & 7) - 3, g.X2);
+          const int Y = wrapc(pos_y(pp) + ((f >> 12) & 7) - 3, g.Y2);
+          const int Z = wrapc(pos_z(pp) + ((f >> 15) & 7) - 3, g.Z2);
+          val = occ[site_of(g, X, Y, Z)];
+        }
+        s.box[q * kBoxBytes + bi] = val;
+      }
+      gsync();
+      const int q = gp.gl >> 3, k = gp.gl & 7;
+      double r = 0.0;
+      int vv = -1;
+      if (q < np) {
+        vv = s.aff[p0 + q];
+        int A;
+        r = eval_box<Real>(s.box + q * kBoxBytes, k, S, s.D1, s.D2, s.e0, nu, kT, A);
+        s.spec[vv * 8 + k] = (uint8_t)A;
+      }
+      // Partial sums over directions: part[v][k] = r0 + r1 + ... + rk.
+      double acc = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < 8; ++mm) {
+        const double x = __shfl(r, gp.base + (q << 3) + mm, 64);
+        if (mm == 0) acc = x;
+        else if (mm <= k) acc = acc + x;
+      }
+      if (q < np) s.part[vv * 8 + k] = acc;
+      gsync();
+    }
+  }
+
+  // Distinct parents (index >> 3) of an ascending list.
+  __device__ int parents(const int *in, int n_in, int *out) {
+    int n_out = 0;
+    for (int b0 = 0; b0 < n_in; b0 += G) {
+      const int idx = b0 + gp.gl;
+      bool keep = false;
+      int p = 0;
+      if (idx < n_in) {
+        p = in[idx] >> 3;
+        keep = (idx == 0) || ((in[idx - 1] >> 3) != p);
+      }
+      const uint64_t m = gp.ballot(keep);
+      if (keep) out[n_out + __popcll(m & gp.lanes_below())] = p;
+      n_out += __popcll(m);
+    }
+    gsync();
+    return n_out;
+  }
+
+  // Re-sums the level-l groups listed in grp[0..ng).
+  __device__ void fold_level(int l, const int *grp, int ng) {
+    constexpr int P = G / 8;
+    for (int p0 = 0; p0 < ng; p0 += P) {
+      const int q = gp.gl >> 3, c = gp.gl & 7;
+      const bool live = q < min(P, ng - p0);
+      int base = 0, cnt = 0;
+      double x = 0.0;
+      if (live) {
+        base = grp[p0 + q] * 8;
+        cnt = min(8, nl(l) - base);
+        if (c < cnt) x = node_value(l, base + c);
+      }
+      double acc = 0.0;
+#pragma unroll
+      for (int mm = 0; mm < 8; ++mm) {
+        const double y = __shfl(x, gp.base + (q << 3) + mm, 64);
+        if (mm == 0) acc = y;
+        else if (mm <= c) acc = acc + y;
+      }
+      if (live && c < cnt) Q(l)[base + c] = acc;
+      gsync();
+    }
+  }
+
+  __device__ void update_tree(int na) {
+    int n = parents(s.aff, na, s.la);
+    int *cur = s.la, *nxt = s.lb;
+    for (int l = 1; l <= nlev; ++l) {
+      fold_level(l, cur, n);
+      if (l == nlev) break;
+      n = parents(cur, n, nxt);
+      int *t = cur; cur = nxt; nxt = t;
+    }
+  }
+
+  __device__ double gamma_tot() const { return Q(nlev)[nl(nlev) - 1]; }
+
+  __device__ void run(int lat) {
+    const LatDesc *d = a.descs + lat;
+    LatState *st = a.states + lat;
+    const int gl = gp.gl;
+    g = make_geo(d->lx, d->ly, d->lz);
+    S = d->S;
+    V = S - 1;
+    nv = d->nv;
+    occ = a.occ + d->occ_off;
+    int32_t *slots = a.slots + d->slot_off;
+    akmc_event *evlog = a.log ? a.log + (int64_t)lat * a.log_stride : nullptr;
+    const bool fp32 = sizeof(Real) == 4;
+    for (int x = gl; x < 64; x += G) {
+      s.D1[x] = fp32 ? (Real)d->D1f[x] : (Real)d->D1[x];
+      s.D2[x] = fp32 ? (Real)d->D2f[x] : (Real)d->D2[x];
+    }
+    if (gl < 8) s.e0[gl] = fp32 ? (Real)d->e0f[gl] : (Real)d->e0[gl];
+    nu = fp32 ? (Real)d->nuf : (Real)d->nu;
+    kT = fp32 ? (Real)d->kTf : (Real)d->kT;
+    const uint64_t seed = d->seed, stream = d->stream;
+    const int time_mode = d->time_mode;
+    const bool full = a.refresh_full != 0;
+
+    nlev = 1;
+    while (nl(nlev) > 8 && nlev < kMaxLevels) ++nlev;
+
+    double t = st->t;
+    int64_t n = st->n;
+    uint64_t dig = st->digest;
+    int frozen = st->frozen;
+    if (frozen) return;
+
+    for (int v = gl; v < nv; v += G) {
+      int X, Y, Z;
+      pos_of(g, slots[v], X, Y, Z);
+      s.pos[v] = pack_pos(X, Y, Z);
+      s.aff[v] = v;
+    }
+    gsync();
+    refresh(nv);
+    update_tree(nv);
+    double gtot = gamma_tot();
+    frozen = !(gtot > 0.0);
+
+    for (int64_t e = 0; e < a.n_events && !frozen; ++e) {
+      const int ce = (int)(e % G);
+      if (ce == 0) {
+        double u1, u2;
+        event_uniforms(seed, stream, n + gl, u1, u2);
+        s.ru1[gl] = u1;
+        s.rw[gl] = -log(u2);
+        gsync();
+      }
+      const double u1 = s.ru1[ce], w = s.rw[ce];
+      double tgt = u1 * gtot;
+
+      // Selection: descend the tree of partial sums.
+      int node = 0;
+      for (int l = nlev; l >= 1; --l) {
+        const int base = (l == nlev) ? 0 : node * 8;
+        const int cnt = min(8, nl(l) - base);
+        const double *qq = Q(l) + base;
+        const bool in = gl < cnt;
+        const double qv = in ? qq[gl] : 0.0;
+        uint64_t m = gp.ballot(in && (qv > tgt)) & 0xffull;
+        int c;
+        if (m) {
+          c = __ffsll((unsigned long long)m) - 1;
+        } else {
+          const double cv = in ? node_value(l, base + gl) : 0.0;
+          const uint64_t m2 = gp.ballot(in && (cv > 0.0)) & 0xffull;
+          c = m2 ? 63 - __clzll((long long)m2) : 0;
+        }
+        if (c > 0) tgt = tgt - qq[c - 1];
+        node = base + c;
+      }
+      const int v = node;
+      int k;
+      {
+        const bool in = gl < 8;
+        const double pv = in ? s.part[v * 8 + gl] : 0.0;
+        uint64_t m = gp.ballot(in && (pv > tgt)) & 0xffull;
+        if (m) {
+          k = __ffsll((unsigned long long)m) - 1;
+        } else {
+          const uint64_t m2 = gp.ballot(in && (s.spec[v * 8 + gl] != V)) & 0xffull;
+          k = m2 ? 63 - __clzll((long long)m2) : 0;
+        }
+      }
+      const int A = s.spec[v * 8 + k];
+      const int pp = s.pos[v];
+      const int X = pos_x(pp), Y = pos_y(pp), Z = pos_z(pp);
+      const int JX = wrapc(X + dir_sx(k), g.X2), JY = wrapc(Y + dir_sy(k), g.Y2),
+                JZ = wrapc(Z + dir_sz(k), g.Z2);
+      const int si = site_of(g, X, Y, Z), sj = site_of(g, JX, JY, JZ);
+      const double dt = time_mode ? 1.0 / gtot : w / gtot;
+      gsync();
+      if (gl == 0) {
+        if (evlog) {
+          akmc_event *ev = evlog + e;
+          ev->n = n;
+          ev->slot = v;
+          ev->from_site = si;
+          ev->to_site = sj;
+          ev->dir = (uint8_t)k;
+          ev->species = (uint8_t)A;
+          ev->pad[0] = 0;
+          ev->pad[1] = 0;
+          ev->gamma_tot = gtot;
+          ev->dt = dt;
+        }
+        occ[si] = (uint8_t)A;
+        occ[sj] = (uint8_t)V;
+        s.pos[v] = pack_pos(JX, JY, JZ);
+      }
+      t += dt;
+      dig = fnv_event(dig, n, si, sj);
+      n += 1;
+      // The swap's stores must be visible to the gathers below.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      gsync();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+
+      int na;
+      if (full) {
+        na = nv;
+      } else {
+        na = 0;
+        for (int b0 = 0; b0 < nv; b0 += G) {
+          const int vv = b0 + gl;
+          bool hit = false;
+          if (vv < nv) {
+            const int q = s.pos[vv];
+            int dx = abs(pos_x(q) - X), dy = abs(pos_y(q) - Y), dz = abs(pos_z(q) - Z);
+            dx = min(dx, g.X2 - dx);
+            dy = min(dy, g.Y2 - dy);
+            dz = min(dz, g.Z2 - dz);
+            hit = max(dx, max(dy, dz)) <= 4;
+          }
+          const uint64_t m = gp.ballot(hit);
+          if (hit) s.aff[na + __popcll(m & gp.lanes_below())] = vv;
+          na += __popcll(m);
+        }
+        gsync();
+      }
+      refresh(na);
+      update_tree(na);
+      gtot = gamma_tot();
+      frozen = !(gtot > 0.0);
+    }
+
+    for (int v = gl; v < nv; v += G) {
+      const int q = s.pos[v];
+      slots[v] = site_of(g, pos_x(q), pos_y(q), pos_z(q));
+    }
+    if (gl == 0) {
+      st->t = t;
+      st->n = n;
+      st->digest = dig;
+      st->gamma_tot = gtot;
+      st->frozen = frozen;
+    }
+    gsync();
+  }
+};
+
+template <int G, int WAVES, bool FP32>
+__global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayout L) {
+  using Real = typename std::conditional<FP32, float, double>::type;
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  Group<G> gp;
+  gp.gw = lane / G;
+  gp.gl = lane % G;
+  gp.base = gp.gw * G;
+  const int gib = wave * (64 / G) + gp.gw;
+  unsigned char *mine = lds + (size_t)gib * L.bytes;
+
+  // This lane's share of the footprint gathers: element f = gl + G*m of the
+  // (G/8) boxes of a refresh pass.  Packed: box index (9 bits), offsets + 3
+  // (3 x 3 bits), box number q (6 bits), centre flag (bit 24); -1 if none.
+  int foot[8];
+  constexpr int P = G / 8;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int f = gp.gl + G * m;
+    if (f >= P * kFootN) {
+      foot[m] = -1;
+      continue;
+    }
+    const int q = f / kFootN, e = f % kFootN;
+    if (e == kFootN - 1) {
+      foot[m] = kBoxC | (q << 18) | (1 << 24);
+    } else {
+      const int dx = kFoot.d[e][0], dy = kFoot.d[e][1], dz = kFoot.d[e][2];
+      const int bi = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+      foot[m] = bi | ((dx + 3) << 9) | ((dy + 3) << 12) | ((dz + 3) << 15) | (q << 18);
+    }
+  }
+
+  Runner<G, Real> run(a, L, gp, foot, mine);
+  for (;;) {
+    int idx = 0;
+    if (gp.gl == 0) idx = atomicAdd(a.queue, 1);
+    idx = gp.bcast(idx, 0);
+    if (idx >= a.n_lat) break;
+    run.run(a.order[idx]);
+  }
+}
+
+__global__ void k_queue_reset(int32_t *queue) { *queue = 0; }
+
+hipError_t launch_queue_reset(int32_t *queue, hipStream_t stream) {
+  hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(1), 0, stream, queue);
+  return hipGetLastError();
+}
+
+size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision) {
+  const GroupLayout L = make_layout(nv_max, group_lanes, precision == AKMC_FP32);
+  return (size_t)L.bytes * (size_t)(64 / group_lanes) * (size_t)waves_per_block;
+}
+
+template <int G, int W, bool FP32>
+static hipError_t launch_one(const LoopArgs &a, const Schedule &s, hipStream_t stream) {
+  const GroupLayout L = make_layout(a.nv_max, G, FP32 ? 1 : 0);
+  const size_t lds = (size_t)L.bytes * (64 / G) * W;
+  auto kern = k_event_loop<G, W, FP32>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  int blocks = s.blocks;
+  const int groups_per_block = (64 / G) * W;
+  const int need = (a.n_lat + groups_per_block - 1) / groups_per_block;
+  if (blocks <= 0 || blocks > need) blocks = need;
+  hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * W), lds, stream, a, L);
+  return hipGetLastError();
+}
+
+template <int G, bool FP32>
+static hipError_t launch_w(const LoopArgs &a, const Schedule &s, hipStream_t stream) {
+  switch (s.waves_per_block) {
+    case 2: return launch_one<G, 2, FP32>(a, s, stream);
+    case 4: return launch_one<G, 4, FP32>(a, s, stream);
+    default: return launch_one<G, 1, FP32>(a, s, stream);
+  }
+}
+
+template <bool FP32>
+static hipError_t launch_g(const LoopArgs &a, const Schedule &s, hipStream_t stream) {
+  switch (s.group_lanes) {
+    case 8: return launch_w<8, FP32>(a, s, stream);
+    case 16: return launch_w<16, FP32>(a, s, stream);
+    case 32: return launch_w<32, FP32>(a, s, stream);
+    default: return launch_w<64, FP32>(a, s, stream);
+  }
+}
+
+hipError_t launch_event_loop(const LoopArgs &a, int precision, int refresh_full,
+                             const Schedule &s, hipStream_t stream) {
+  LoopArgs b = a;
+  b.refresh_full = refresh_full;
+  hipError_t e = launch_queue_reset(a.queue, stream);
+  if (e != hipSuccess) return e;
+  return precision == AKMC_FP32 ? launch_g<true>(b, s, stream) : launch_g<false>(b, s, stream);
+}
+
+}  // namespace akmc

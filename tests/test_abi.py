@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports every function include/akmc.h declares,
+and rejects bad arguments on the host before touching a GPU."""
+import ctypes as C
+
+import numpy as np
+import pytest
+
+from paper_2604_24091_amd import akmc
+from paper_2604_24091_amd import workloads as W
+
+
+def test_library_exports_every_declared_symbol():
+    names = akmc.header_functions()
+    assert len(names) >= 15
+    L = akmc.lib()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    assert akmc.status_string(akmc.OK) == "ok"
+    assert "frozen" in akmc.status_string(akmc.ERR_FROZEN)
+
+
+def test_workspace_bytes_and_validation():
+    spec = W.fe_cu_2k()
+    p = akmc.make_params(spec)
+    n = akmc.workspace_bytes(p, 1)
+    assert n >= spec.n_sites
+    bad = akmc.make_params(spec)
+    bad.lx = 2
+    with pytest.raises(akmc.AkmcError) as e:
+        akmc.workspace_bytes(bad, 1)
+    assert e.value.status == akmc.ERR_INVALID and "edges" in str(e.value)
+    bad = akmc.make_params(spec)
+    bad.eps1[1] += 0.1            # breaks symmetry
+    with pytest.raises(akmc.AkmcError):
+        akmc.workspace_bytes(bad, 1)
+    bad = akmc.make_params(spec)
+    bad.temperature = -1.0
+    with pytest.raises(akmc.AkmcError):
+        akmc.workspace_bytes(bad, 1)
+    with pytest.raises(akmc.AkmcError):
+        akmc.workspace_bytes(p, akmc.MAX_VACANCIES + 1)
+
+
+def test_create_rejects_null_and_bad_codes_without_gpu():
+    spec = W.fe_cu_2k()
+    p = akmc.make_params(spec)
+    L = akmc.lib()
+    h = C.c_void_p()
+    st = L.akmc_lattice_create(C.byref(p), None, None, None, 0, None, C.byref(h))
+    assert st == akmc.ERR_INVALID
+    occ = spec.occ.copy()
+    occ[5] = 9
+    fake_ws = C.c_void_p(256 * 1024)     # never dereferenced: validation fails first
+    st = L.akmc_lattice_create(C.byref(p), occ.ctypes.data, None, fake_ws, 1 << 20, None, C.byref(h))
+    assert st == akmc.ERR_INVALID and "code" in akmc.last_error()
+    st = L.akmc_lattice_create(C.byref(p), spec.occ.ctypes.data, None, fake_ws, 16, None, C.byref(h))
+    assert st == akmc.ERR_WORKSPACE
+    misaligned = C.c_void_p(256 * 1024 + 8)
+    st = L.akmc_lattice_create(C.byref(p), spec.occ.ctypes.data, None, misaligned, 1 << 20, None, C.byref(h))
+    assert st == akmc.ERR_INVALID
+    bad_slots = np.array([0], dtype=np.int32)
+    st = L.akmc_lattice_create(C.byref(p), spec.occ.ctypes.data, bad_slots.ctypes.data, fake_ws, 1 << 20, None, C.byref(h))
+    assert st == akmc.ERR_INVALID
+
+
+def test_struct_sizes_match_header():
+    assert C.sizeof(akmc.Event) == 40
+    assert C.sizeof(akmc.Params) == 4 * 4 + 8 * (64 + 64 + 8) + 8 * 3 + 8 * 2 + 8 * 3 + 4 * 4

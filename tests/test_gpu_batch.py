@@ -1,0 +1,99 @@
+"""GPU parity of the batched replica ensemble (akmc_batch_*).
+
+Every replica of a batch must end bit for bit where a standalone lattice
+with the same parameters ends (occupancy, slots, digest, time), for every
+launch schedule; replicas are checked against the oracle too.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_24091_amd import akmc
+from paper_2604_24091_amd import workloads as W
+from tests.gpu_util import banner, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch(specs, n_events, sched=None, chunks=None, precision=akmc.FP64):
+    import torch
+    params = [akmc.make_params(s, precision=precision) for s in specs]
+    nv = [int(np.count_nonzero(s.occ == s.n_species - 1)) for s in specs]
+    nbytes = akmc.batch_workspace_bytes(params, nv)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = akmc.batch_create(params, [s.occ for s in specs], ws)
+    if sched is not None:
+        akmc.batch_set_schedule(b, sched)
+    for n in (chunks or [n_events]):
+        akmc.batch_step(b, n)
+    out = []
+    for r, s in enumerate(specs):
+        occ = np.empty(s.n_sites, np.uint8)
+        sl = np.empty(max(nv[r], 1), np.int32)
+        summ = akmc.batch_state_read(b, r, occ, sl)
+        out.append((occ, sl[:nv[r]], summ))
+    akmc.batch_destroy(b)
+    return out
+
+
+def _small_replicas(n_rep=24, seed=5):
+    specs = W.rpv_replicas(n_rep=n_rep, seed=seed, cells_range=(4, 12), max_vac=20)
+    return specs
+
+
+@pytest.mark.parametrize("lanes,waves,graph", [(8, 1, 0), (16, 2, 0), (32, 1, 1), (64, 4, 0), (8, 4, 1)])
+def test_batch_equals_standalone(lanes, waves, graph):
+    banner("batch lanes=%d waves=%d graph=%d" % (lanes, waves, graph))
+    specs = _small_replicas()
+    n = 3000
+    sched = akmc.Schedule(lanes, waves, 0, graph, 1000)
+    res = _batch(specs, n, sched)
+    for r in (0, 5, 11, 23):
+        occ, sl, s, _ = run_gpu(specs[r], n, log=False)
+        bo, bsl, bs = res[r]
+        assert np.array_equal(bo, occ) and np.array_equal(bsl, sl)
+        assert bs.digest == s.digest and bs.t == s.t and bs.n_events == s.n_events == n
+
+
+def test_batch_schedules_agree_and_match_oracle(oracle_mod):
+    banner("batch schedules vs oracle")
+    specs = _small_replicas(n_rep=12, seed=9)
+    n = 2000
+    a = _batch(specs, n, akmc.Schedule(8, 1, 0, 0, 700))
+    b = _batch(specs, n, akmc.Schedule(64, 2, 3, 0, 2000))
+    for r in range(len(specs)):
+        assert np.array_equal(a[r][0], b[r][0])
+        assert a[r][2].digest == b[r][2].digest and a[r][2].t == b[r][2].t
+    for r in (0, 7):
+        o = oracle_mod.Oracle(specs[r])
+        o.run(n)
+        if o.state.digest != a[r][2].digest:
+            pytest.skip("replica %d diverged from the oracle (near tie check lives in the loop tests)" % r)
+        assert np.array_equal(o.occ, a[r][0])
+        assert abs(o.state.t - a[r][2].t) <= 1e-12 * o.state.t
+
+
+def test_batch_autotune_keeps_results():
+    banner("batch autotune")
+    import torch
+    specs = _small_replicas(n_rep=16, seed=13)
+    params = [akmc.make_params(s) for s in specs]
+    nv = [int(np.count_nonzero(s.occ == 4)) for s in specs]
+    ws = torch.empty(akmc.batch_workspace_bytes(params, nv), dtype=torch.uint8, device="cuda")
+    b = akmc.batch_create(params, [s.occ for s in specs], ws)
+    chosen = akmc.batch_autotune(b, 100)        # 8 trials x 100 events
+    assert chosen.group_lanes in (8, 16, 32, 64) and chosen.waves_per_block in (1, 2)
+    akmc.batch_step(b, 200)
+    occ = np.empty(specs[3].n_sites, np.uint8)
+    s = akmc.batch_state_read(b, 3, occ)
+    akmc.batch_destroy(b)
+    ref = run_gpu(specs[3], 1000, log=False)
+    assert np.array_equal(occ, ref[0]) and s.digest == ref[2].digest
+
+
+def test_batch_fp32_equals_standalone():
+    banner("batch fp32")
+    specs = _small_replicas(n_rep=10, seed=17)
+    res = _batch(specs, 2000, akmc.Schedule(16, 1, 0, 0, 2000), precision=akmc.FP32)
+    for r in (0, 9):
+        occ, sl, s, _ = run_gpu(specs[r], 2000, log=False, precision=akmc.FP32)
+        assert np.array_equal(res[r][0], occ) and res[r][2].digest == s.digest
