@@ -5,7 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include "../../include/akmc.h"
+#include "akmc.h"
 
 namespace akmc {
 
@@ -33,6 +33,14 @@ struct LatDesc {
   double beta;                // 1/kT
   float betaf;
   int32_t pad_[1];
+  // Log-rate tables of the sweep:  ln r = Cn[A][s_p] + (beta/2)(G'_A(j) - G'_A(p))
+  // with Cn[A][s] = ln(nu) - beta*e0[A] - (beta/2)*K[A][s];  C2f is Cn*log2(e)
+  // in binary32 and h2f = (beta/2)*log2(e), for a base-2 exponential.
+  double Cn[64];
+  double half_beta;
+  float C2f[64];
+  float h2f;
+  int32_t pad2_[1];
 };
 
 // Mutable per-lattice state.
