@@ -226,6 +226,96 @@ akmc_status akmc_batch_state_read(akmc_batch b, int32_t r, uint8_t *occ_host,
 
 akmc_status akmc_batch_destroy(akmc_batch b);
 
+/* ----------------------------------------------------- learned barrier */
+
+/* A small network predicts the barrier Ea of a candidate from the species in
+ * the bonds the jump changes; the pair model stays as the fallback and as
+ * the judge of its error.  It applies the paper's reformulation of per-atom
+ * network evaluation as batched matrix products on matrix units with
+ * reduced precision and fused layers (Sec. III-B1), trained with AdamW at
+ * batch 256 (Sec. IV-C).
+ *   input   27 footprint slots of the candidate in the frame where the jump
+ *           points along (+,+,+): slot 0 the moving species, 1..7 N1(i)
+ *           without j, 8..13 N2(i), 14..20 N1(j) without i, 21..26 N2(j),
+ *           each one-hot over S codes, zero-padded to 32*ceil(27*S/32);
+ *   network 128 and 128 GELU(tanh) units, one output y; Ea = mu + sigma*y;
+ *           bfloat16 weights and activations on the matrix cores with
+ *           binary32 accumulation, binary32 biases and optimiser state.
+ * The weights live in a caller-owned device blob. */
+
+typedef struct akmc_train_cfg {
+    int32_t batch;          /* rows per step, multiple of 16 (256) */
+    int32_t epochs;         /* passes over the data set */
+    float lr;               /* initial learning rate */
+    float lr_final;         /* learning rate of the last step (cosine decay) */
+    float beta1, beta2, eps;
+    float weight_decay;     /* decoupled (AdamW) */
+    int32_t shuffle;        /* 1: a fresh keyed permutation of the rows per epoch; 0: data order */
+    int32_t pad_;
+    uint64_t seed;          /* key of the row permutations */
+} akmc_train_cfg;
+
+/* Device bytes of the weight blob for n_species codes (2..8). */
+akmc_status akmc_mlp_blob_bytes(int32_t n_species, size_t *bytes);
+
+/* Initialises a blob: uniform random weights from the Philox stream of
+ * seed, zero biases and optimiser moments, output scale Ea = mu + sigma*y.
+ * Asynchronous on hip_stream. */
+akmc_status akmc_mlp_init(void *d_blob, int32_t n_species, uint64_t seed, float mu,
+                          float sigma, void *hip_stream);
+
+/* Copies binary32 parameters in (host_params: the vector W1[K1][128],
+ * b1[128], W2[128][128], b2[128], w3[128], b3[1], row-major input x output)
+ * and clears the optimiser state, or out (get).  Synchronous. */
+akmc_status akmc_mlp_set_params(void *d_blob, int32_t n_species, const float *host_params,
+                                float mu, float sigma, void *hip_stream);
+akmc_status akmc_mlp_get_params(const void *d_blob, int32_t n_species, float *host_params,
+                                float *mu, float *sigma, void *hip_stream);
+akmc_status akmc_mlp_param_count(int32_t n_species, int32_t *count);
+
+/* Species codes of the 27 slots (d_env: uint8 [n][8][27]) and the pair-model
+ * barrier (d_ea: float [n][8], +inf for an inadmissible jump; may be NULL)
+ * of every candidate of the mode's site set (as in rates_eval). */
+akmc_status akmc_env_encode(akmc_handle h, int32_t mode, const int32_t *d_sites, int64_t n_sites,
+                            uint8_t *d_env, float *d_ea);
+
+/* Records in the blob the largest per-species count of each of the four bond
+ * groups over a data set, and which moving species occur; a candidate beyond
+ * any of them is out of distribution and falls back to the pair model in the
+ * event loop. */
+akmc_status akmc_mlp_fit_ood(void *d_blob, int32_t n_species, const uint8_t *d_env, int64_t n,
+                             void *hip_stream);
+
+/* Barriers of n encoded candidates (d_ea: float [n]).  Asynchronous. */
+akmc_status akmc_mlp_forward(const void *d_blob, int32_t n_species, const uint8_t *d_env,
+                             int64_t n, float *d_ea, void *hip_stream);
+
+/* Uses the blob's network for the barriers of a lattice created with
+ * barrier_model AKMC_BARRIER_MLP (precision AKMC_FP32): inside the event
+ * loop every refreshed candidate's 27 slot codes are staged in LDS and
+ * evaluated on the matrix cores; candidates out of distribution (see
+ * akmc_mlp_fit_ood) use the pair barrier and are counted in
+ * akmc_summary.n_ood.  The blob is borrowed and must outlive the handle.
+ * Synchronises the handle's stream. */
+akmc_status akmc_mlp_attach(akmc_handle h, const void *d_blob);
+
+/* Scratch bytes of training with this batch. */
+akmc_status akmc_mlp_train_workspace_bytes(int32_t n_species, int32_t batch, size_t *bytes);
+
+/* Trains on n rows (d_env [n][27] codes, d_ea [n] targets; rows whose slot 0
+ * is the vacancy code are ignored) with mean-squared error on the
+ * standardised barrier and AdamW.  d_loss: float per step or NULL.
+ * Asynchronous. */
+akmc_status akmc_mlp_train(void *d_blob, int32_t n_species, const uint8_t *d_env,
+                           const float *d_ea, int64_t n, const akmc_train_cfg *cfg, float *d_loss,
+                           void *d_work, size_t work_bytes, void *hip_stream);
+
+/* Gradient of the mean loss over rows 0..n-1 (n <= batch of the workspace)
+ * at the current weights, without an update: d_grad float [param_count]. */
+akmc_status akmc_mlp_grad(const void *d_blob, int32_t n_species, const uint8_t *d_env,
+                          const float *d_ea, int32_t n, float *d_grad, float *d_loss,
+                          void *d_work, size_t work_bytes, void *hip_stream);
+
 /* ------------------------------------------------------------ messages */
 
 const char *akmc_status_string(akmc_status s);

@@ -52,6 +52,13 @@ class Summary(C.Structure):
                 ("n_vacancies", C.c_int32), ("frozen", C.c_int32)]
 
 
+class TrainCfg(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("epochs", C.c_int32), ("lr", C.c_float),
+                ("lr_final", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("weight_decay", C.c_float), ("shuffle", C.c_int32),
+                ("pad_", C.c_int32), ("seed", C.c_uint64)]
+
+
 class Schedule(C.Structure):
     _fields_ = [("group_lanes", C.c_int32), ("waves_per_block", C.c_int32),
                 ("blocks", C.c_int32), ("use_graph", C.c_int32), ("chunk_events", C.c_int64)]
@@ -94,6 +101,24 @@ def lib():
         L.akmc_batch_autotune.argtypes = [vp, C.c_int64, C.POINTER(Schedule)]
         L.akmc_batch_state_read.argtypes = [vp, C.c_int32, vp, vp, C.POINTER(Summary)]
         L.akmc_batch_destroy.argtypes = [vp]
+        i32 = C.c_int32
+        L.akmc_mlp_blob_bytes.argtypes = [i32, C.POINTER(sz)]
+        L.akmc_mlp_param_count.argtypes = [i32, C.POINTER(i32)]
+        L.akmc_mlp_init.argtypes = [vp, i32, C.c_uint64, C.c_float, C.c_float, vp]
+        L.akmc_mlp_set_params.argtypes = [vp, i32, vp, C.c_float, C.c_float, vp]
+        L.akmc_mlp_get_params.argtypes = [vp, i32, vp, C.POINTER(C.c_float), C.POINTER(C.c_float), vp]
+        L.akmc_env_encode.argtypes = [vp, i32, vp, C.c_int64, vp, vp]
+        L.akmc_mlp_fit_ood.argtypes = [vp, i32, vp, C.c_int64, vp]
+        L.akmc_mlp_forward.argtypes = [vp, i32, vp, C.c_int64, vp, vp]
+        L.akmc_mlp_train_workspace_bytes.argtypes = [i32, i32, C.POINTER(sz)]
+        L.akmc_mlp_train.argtypes = [vp, i32, vp, vp, C.c_int64, C.POINTER(TrainCfg), vp, vp, sz, vp]
+        L.akmc_mlp_grad.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, sz, vp]
+        L.akmc_mlp_attach.argtypes = [vp, vp]
+        for name in ("akmc_mlp_blob_bytes", "akmc_mlp_param_count", "akmc_mlp_init",
+                     "akmc_mlp_set_params", "akmc_mlp_get_params", "akmc_env_encode",
+                     "akmc_mlp_fit_ood", "akmc_mlp_forward", "akmc_mlp_train_workspace_bytes",
+                     "akmc_mlp_train", "akmc_mlp_grad", "akmc_mlp_attach"):
+            getattr(L, name).restype = C.c_int32
         L.akmc_status_string.argtypes = [C.c_int32]
         L.akmc_status_string.restype = C.c_char_p
         L.akmc_last_error.restype = C.c_char_p
@@ -260,6 +285,89 @@ def batch_state_read(b: int, r: int, occ_host: Optional[np.ndarray] = None,
 
 def batch_destroy(b: int):
     _check(lib().akmc_batch_destroy(b), "batch_destroy")
+
+
+def mlp_blob_bytes(S: int) -> int:
+    n = C.c_size_t()
+    _check(lib().akmc_mlp_blob_bytes(int(S), C.byref(n)), "mlp_blob_bytes")
+    return n.value
+
+
+def mlp_param_count(S: int) -> int:
+    n = C.c_int32()
+    _check(lib().akmc_mlp_param_count(int(S), C.byref(n)), "mlp_param_count")
+    return n.value
+
+
+def mlp_init(blob, S: int, seed: int, mu: float, sigma: float, stream=None):
+    _check(lib().akmc_mlp_init(_ptr(blob), int(S), int(seed), float(mu), float(sigma), _stream(stream)),
+           "mlp_init")
+
+
+def mlp_set_params(blob, S: int, params: np.ndarray, mu: float, sigma: float, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().akmc_mlp_set_params(_ptr(blob), int(S), p.ctypes.data, float(mu), float(sigma),
+                                     _stream(stream)), "mlp_set_params")
+
+
+def mlp_get_params(blob, S: int, stream=None):
+    p = np.empty(mlp_param_count(S), dtype=np.float32)
+    mu, sg = C.c_float(), C.c_float()
+    _check(lib().akmc_mlp_get_params(_ptr(blob), int(S), p.ctypes.data, C.byref(mu), C.byref(sg),
+                                     _stream(stream)), "mlp_get_params")
+    return p, mu.value, sg.value
+
+
+def env_encode(h: int, mode: int, sites, n_sites: int, env_out, ea_out=None):
+    _check(lib().akmc_env_encode(h, int(mode), _ptr(sites), int(n_sites), _ptr(env_out), _ptr(ea_out)),
+           "env_encode")
+
+
+def mlp_fit_ood(blob, S: int, env, n: int, stream=None):
+    _check(lib().akmc_mlp_fit_ood(_ptr(blob), int(S), _ptr(env), int(n), _stream(stream)), "mlp_fit_ood")
+
+
+def mlp_forward(blob, S: int, env, n: int, ea_out, stream=None):
+    _check(lib().akmc_mlp_forward(_ptr(blob), int(S), _ptr(env), int(n), _ptr(ea_out), _stream(stream)),
+           "mlp_forward")
+
+
+def mlp_train_workspace_bytes(S: int, batch: int) -> int:
+    n = C.c_size_t()
+    _check(lib().akmc_mlp_train_workspace_bytes(int(S), int(batch), C.byref(n)), "mlp_train_workspace_bytes")
+    return n.value
+
+
+def mlp_train(blob, S: int, env, ea, n: int, cfg: TrainCfg, work, loss=None, stream=None):
+    _check(lib().akmc_mlp_train(_ptr(blob), int(S), _ptr(env), _ptr(ea), int(n), C.byref(cfg),
+                                _ptr(loss), _ptr(work), work.numel(), _stream(stream)), "mlp_train")
+
+
+def mlp_grad(blob, S: int, env, ea, n: int, grad_out, work, loss=None, stream=None):
+    _check(lib().akmc_mlp_grad(_ptr(blob), int(S), _ptr(env), _ptr(ea), int(n), _ptr(grad_out),
+                               _ptr(loss), _ptr(work), work.numel(), _stream(stream)), "mlp_grad")
+
+
+def mlp_attach(h: int, blob):
+    _check(lib().akmc_mlp_attach(h, _ptr(blob)), "mlp_attach")
+
+
+def pack_params(p: dict) -> np.ndarray:
+    """Flat binary32 parameter vector in the library's order from a dict with
+    W1 (K1 x 128), b1, W2 (128 x 128), b2, w3, b3."""
+    return np.concatenate([np.asarray(p[k], dtype=np.float64).reshape(-1)
+                           for k in ("W1", "b1", "W2", "b2", "w3", "b3")]).astype(np.float32)
+
+
+def unpack_params(v: np.ndarray, S: int) -> dict:
+    k1 = 32 * ((27 * S + 31) // 32)
+    H = 128
+    out, o = {}, 0
+    for k, shape in (("W1", (k1, H)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("w3", (H,)), ("b3", (1,))):
+        n = int(np.prod(shape))
+        out[k] = np.asarray(v[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    return out
 
 
 # ------------------------------------------------------ conveniences

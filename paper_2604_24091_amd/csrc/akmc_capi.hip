@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "akmc_internal.hpp"
+#include "akmc_mlp.hpp"
 
 using namespace akmc;
 
@@ -118,6 +119,17 @@ LatDesc make_desc(const akmc_params *p, int nv) {
   d.kTf = (float)d.kT;
   d.beta = 1.0 / d.kT;
   d.betaf = (float)d.beta;
+  d.half_beta = 0.5 * d.beta;
+  const double log2e = 1.4426950408889634074;
+  const double lnnu = std::log(d.nu);
+  for (int A = 0; A < S; ++A)
+    for (int s = 0; s < S; ++s) {
+      const double e0 = A < S - 1 ? d.e0[A] : 0.0;
+      const double c = lnnu - d.beta * e0 - d.half_beta * d.K[A * S + s];
+      d.Cn[A * S + s] = c;
+      d.C2f[A * S + s] = (float)(c * log2e);
+    }
+  d.h2f = (float)(d.half_beta * log2e);
   return d;
 }
 
@@ -179,6 +191,7 @@ struct akmc_lattice {
   int32_t *d_order, *d_queue, *d_slots;
   double *d_scratch;
   uint8_t *d_occ;
+  const unsigned char *mlp_blob = nullptr;
 };
 
 extern "C" {
@@ -200,8 +213,8 @@ akmc_status akmc_lattice_create(const akmc_params *p, const uint8_t *occ_host,
   if (st != AKMC_OK) return st;
   if (!occ_host || !d_ws || !out) return fail(AKMC_ERR_INVALID, "NULL occupancy, workspace or out");
   if (!aligned(d_ws)) return fail(AKMC_ERR_INVALID, "workspace must be 256-byte aligned");
-  if (p->barrier_model != AKMC_BARRIER_PAIR)
-    return fail(AKMC_ERR_UNSUPPORTED, "barrier_model MLP needs the surrogate entry points");
+  if (p->barrier_model == AKMC_BARRIER_MLP && p->precision != AKMC_FP32)
+    return fail(AKMC_ERR_UNSUPPORTED, "the learned barrier gives binary32 rates: use precision AKMC_FP32");
   const int64_t N = n_sites_of(p);
   std::vector<int32_t> slots;
   st = build_slots(p, occ_host, slot_sites_host, slots);
@@ -291,13 +304,18 @@ akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log) {
   a.queue = h->d_queue;
   a.n_lat = 1;
   a.nv_max = h->nv;
+  const bool mlp = h->p.barrier_model == AKMC_BARRIER_MLP;
+  if (mlp && !h->mlp_blob) return fail(AKMC_ERR_INVALID, "barrier_model MLP: attach weights with akmc_mlp_attach first");
+  a.mlp_blob = h->mlp_blob;
   Schedule s{64, 1, 1};
   for (int64_t done = 0; done < n_events; done += kChunkEvents) {
     const int64_t n = std::min(kChunkEvents, n_events - done);
     a.n_events = n;
     a.log = d_log ? d_log + done : nullptr;
     a.log_stride = n;
-    hipError_t e = launch_event_loop(a, h->p.precision, h->p.refresh == AKMC_REFRESH_FULL, s, h->stream);
+    const int full = h->p.refresh == AKMC_REFRESH_FULL;
+    hipError_t e = mlp ? launch_event_loop_mlp(a, full, h->p.n_species, h->stream)
+                       : launch_event_loop(a, h->p.precision, full, s, h->stream);
     if (e != hipSuccess) return hip_fail(e, "kmc_step launch");
   }
   return AKMC_OK;
@@ -673,6 +691,219 @@ akmc_status akmc_batch_destroy(akmc_batch b) {
   for (auto &kv : b->graphs) hipGraphExecDestroy(kv.second);
   if (b->cap_stream) hipStreamDestroy(b->cap_stream);
   delete b;
+  return AKMC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------- surrogate
+
+namespace {
+akmc_status check_species(int32_t S) {
+  if (S < 2 || S > AKMC_MAX_SPECIES) return fail(AKMC_ERR_INVALID, "n_species must lie in [2, 8]");
+  return AKMC_OK;
+}
+int even_bits(int64_t n) {
+  int b = 2;
+  while ((int64_t(1) << b) < n) b += 2;
+  return b;
+}
+}  // namespace
+
+extern "C" {
+
+akmc_status akmc_mlp_blob_bytes(int32_t n_species, size_t *bytes) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!bytes) return fail(AKMC_ERR_INVALID, "bytes is NULL");
+  *bytes = mlp_layout(n_species).total;
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_param_count(int32_t n_species, int32_t *count) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!count) return fail(AKMC_ERR_INVALID, "count is NULL");
+  *count = mlp_nparams(n_species);
+  return AKMC_OK;
+}
+
+static akmc_status write_header(void *d_blob, int32_t S, float mu, float sigma, hipStream_t st) {
+  MlpHeader h;
+  std::memset(&h, 0, sizeof(h));
+  h.S = S;
+  h.k1 = mlp_k1(S);
+  h.nparams = mlp_nparams(S);
+  h.step = 0;
+  h.mu = mu;
+  h.sigma = sigma;
+  HIP_TRY(hipMemcpyAsync(d_blob, &h, sizeof(h), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_init(void *d_blob, int32_t n_species, uint64_t seed, float mu, float sigma,
+                          void *hip_stream) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!d_blob || !aligned(d_blob)) return fail(AKMC_ERR_INVALID, "blob must be 256-byte aligned device memory");
+  if (!(sigma > 0.f) || !std::isfinite(mu)) return fail(AKMC_ERR_INVALID, "need finite mu and sigma > 0");
+  hipStream_t st = (hipStream_t)hip_stream;
+  s = write_header(d_blob, n_species, mu, sigma, st);
+  if (s != AKMC_OK) return s;
+  hipError_t e = launch_mlp_init((unsigned char *)d_blob, n_species, seed, st);
+  if (e != hipSuccess) return hip_fail(e, "mlp_init launch");
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_set_params(void *d_blob, int32_t n_species, const float *host_params,
+                                float mu, float sigma, void *hip_stream) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!d_blob || !aligned(d_blob) || !host_params) return fail(AKMC_ERR_INVALID, "bad blob or parameters");
+  if (!(sigma > 0.f)) return fail(AKMC_ERR_INVALID, "sigma must be > 0");
+  hipStream_t st = (hipStream_t)hip_stream;
+  s = write_header(d_blob, n_species, mu, sigma, st);
+  if (s != AKMC_OK) return s;
+  const MlpLayout L = mlp_layout(n_species);
+  const size_t nb = sizeof(float) * (size_t)mlp_nparams(n_species);
+  unsigned char *b = (unsigned char *)d_blob;
+  HIP_TRY(hipMemcpyAsync(b + L.params, host_params, nb, hipMemcpyHostToDevice, st));
+  std::vector<float> zero((size_t)mlp_nparams(n_species), 0.f);
+  HIP_TRY(hipMemcpyAsync(b + L.m, zero.data(), nb, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b + L.v, zero.data(), nb, hipMemcpyHostToDevice, st));
+  hipError_t e = launch_mlp_sync(b, n_species, st);
+  if (e != hipSuccess) return hip_fail(e, "mlp sync launch");
+  HIP_TRY(hipStreamSynchronize(st));
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_get_params(const void *d_blob, int32_t n_species, float *host_params,
+                                float *mu, float *sigma, void *hip_stream) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!d_blob) return fail(AKMC_ERR_INVALID, "blob is NULL");
+  hipStream_t st = (hipStream_t)hip_stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  MlpHeader h;
+  HIP_TRY(hipMemcpy(&h, d_blob, sizeof(h), hipMemcpyDeviceToHost));
+  if (h.S != n_species) return fail(AKMC_ERR_INVALID, "blob holds a different species count");
+  const MlpLayout L = mlp_layout(n_species);
+  if (host_params)
+    HIP_TRY(hipMemcpy(host_params, (const unsigned char *)d_blob + L.params,
+                      sizeof(float) * (size_t)mlp_nparams(n_species), hipMemcpyDeviceToHost));
+  if (mu) *mu = h.mu;
+  if (sigma) *sigma = h.sigma;
+  return AKMC_OK;
+}
+
+akmc_status akmc_env_encode(akmc_handle h, int32_t mode, const int32_t *d_sites, int64_t n_sites,
+                            uint8_t *d_env, float *d_ea) {
+  if (!h || !d_env) return fail(AKMC_ERR_INVALID, "handle or output is NULL");
+  const int32_t *sites;
+  int64_t n;
+  switch (mode) {
+    case AKMC_RATES_VACANCIES: sites = h->d_slots; n = h->nv; break;
+    case AKMC_RATES_SITES:
+      if (n_sites < 0 || (n_sites > 0 && !d_sites)) return fail(AKMC_ERR_INVALID, "bad site list");
+      sites = d_sites; n = n_sites; break;
+    case AKMC_RATES_ALL_SITES: sites = nullptr; n = h->nsites; break;
+    default: return fail(AKMC_ERR_INVALID, "unknown mode");
+  }
+  hipError_t e = launch_env_encode(h->d_desc, h->d_occ, sites, n, d_env, d_ea, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "env_encode launch");
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_fit_ood(void *d_blob, int32_t n_species, const uint8_t *d_env, int64_t n,
+                             void *hip_stream) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!d_blob || (n > 0 && !d_env) || n < 0) return fail(AKMC_ERR_INVALID, "bad blob or data");
+  hipError_t e = launch_ood_fit((unsigned char *)d_blob, d_env, n, n_species, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "ood_fit launch");
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_forward(const void *d_blob, int32_t n_species, const uint8_t *d_env, int64_t n,
+                             float *d_ea, void *hip_stream) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!d_blob || n < 0 || (n > 0 && (!d_env || !d_ea))) return fail(AKMC_ERR_INVALID, "bad arguments");
+  hipError_t e = launch_mlp_forward((const unsigned char *)d_blob, n_species, d_env, n, d_ea,
+                                    (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp_forward launch");
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_attach(akmc_handle h, const void *d_blob) {
+  if (!h || !d_blob) return fail(AKMC_ERR_INVALID, "handle or blob is NULL");
+  if (h->p.barrier_model != AKMC_BARRIER_MLP)
+    return fail(AKMC_ERR_INVALID, "lattice was created with the pair barrier model");
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  MlpHeader hd;
+  HIP_TRY(hipMemcpy(&hd, d_blob, sizeof(hd), hipMemcpyDeviceToHost));
+  if (hd.S != h->p.n_species || hd.k1 != mlp_k1(hd.S))
+    return fail(AKMC_ERR_INVALID, "blob was built for a different species count");
+  h->mlp_blob = (const unsigned char *)d_blob;
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_train_workspace_bytes(int32_t n_species, int32_t batch, size_t *bytes) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (batch <= 0 || batch % 16 || !bytes) return fail(AKMC_ERR_INVALID, "batch must be a positive multiple of 16");
+  *bytes = mlp_partial_bytes(n_species, batch);
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_train(void *d_blob, int32_t n_species, const uint8_t *d_env, const float *d_ea,
+                           int64_t n, const akmc_train_cfg *cfg, float *d_loss, void *d_work,
+                           size_t work_bytes, void *hip_stream) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!d_blob || !d_env || !d_ea || !cfg || !d_work || n <= 0 || n >= (int64_t(1) << 31))
+    return fail(AKMC_ERR_INVALID, "bad training arguments");
+  if (cfg->batch <= 0 || cfg->batch % 16 || cfg->epochs <= 0 || !(cfg->lr > 0.f))
+    return fail(AKMC_ERR_INVALID, "bad training configuration");
+  if (work_bytes < mlp_partial_bytes(n_species, cfg->batch)) return fail(AKMC_ERR_WORKSPACE, "training workspace too small");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t per_epoch = (n + cfg->batch - 1) / cfg->batch;
+  const int64_t total = per_epoch * cfg->epochs;
+  const int bits = even_bits(n);
+  int64_t step = 0;
+  for (int ep = 0; ep < cfg->epochs; ++ep) {
+    uint64_t x[1];
+    // one key per epoch, derived from the seed with a 64-bit mix
+    uint64_t k = cfg->seed + 0x9E3779B97F4A7C15ull * (uint64_t)(ep + 1);
+    k ^= k >> 31; k *= 0xBF58476D1CE4E5B9ull; k ^= k >> 27; k *= 0x94D049BB133111EBull; k ^= k >> 31;
+    x[0] = k | 1ull;
+    for (int64_t b = 0; b < per_epoch; ++b, ++step) {
+      const int rows = (int)std::min<int64_t>(cfg->batch, n - b * cfg->batch);
+      const double frac = total > 1 ? (double)step / (double)(total - 1) : 1.0;
+      const float lr = (float)(cfg->lr_final + 0.5 * (cfg->lr - cfg->lr_final) * (1.0 + std::cos(M_PI * frac)));
+      hipError_t e = launch_mlp_step((unsigned char *)d_blob, n_species, d_env, d_ea, n, cfg->batch,
+                                     rows, b * cfg->batch, cfg->shuffle ? x[0] : 0ull, bits, (float *)d_work, 1, lr,
+                                     cfg->beta1, cfg->beta2, cfg->eps, cfg->weight_decay,
+                                     (int)(step + 1), nullptr, d_loss ? d_loss + step : nullptr, st);
+      if (e != hipSuccess) return hip_fail(e, "mlp training step");
+    }
+  }
+  return AKMC_OK;
+}
+
+akmc_status akmc_mlp_grad(const void *d_blob, int32_t n_species, const uint8_t *d_env,
+                          const float *d_ea, int32_t n, float *d_grad, float *d_loss, void *d_work,
+                          size_t work_bytes, void *hip_stream) {
+  akmc_status s = check_species(n_species);
+  if (s != AKMC_OK) return s;
+  if (!d_blob || !d_env || !d_ea || !d_grad || !d_work || n <= 0) return fail(AKMC_ERR_INVALID, "bad arguments");
+  const int batch = (n + 15) / 16 * 16;
+  if (work_bytes < mlp_partial_bytes(n_species, batch)) return fail(AKMC_ERR_WORKSPACE, "workspace too small");
+  hipError_t e = launch_mlp_step((unsigned char *)d_blob, n_species, d_env, d_ea, n, batch, n, 0, 0,
+                                 2, (float *)d_work, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0, d_grad, d_loss,
+                                 (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "mlp_grad launch");
   return AKMC_OK;
 }
 

@@ -68,6 +68,7 @@ struct LoopArgs {
   int32_t nv_max;             // LDS sizing
   int32_t refresh_full;       // 1: refresh every slot after every event
   int64_t n_events;           // per lattice
+  const unsigned char *mlp_blob;  // surrogate weights (barrier model MLP) or NULL
 };
 
 // LDS carve-up of one lattice group in the event loop.  Every array is
@@ -81,7 +82,7 @@ struct GroupLayout {
   int nv_max, G, fp32, nlev_max;
   int qlen[kMaxLevels + 1];       // elements of level l (1-based)
   int qoff[kMaxLevels + 1];       // element offset of level l in the Q region
-  int off_part, off_q, off_pos, off_aff, off_la, off_lb, off_spec, off_box, off_tab, off_rng;
+  int off_part, off_q, off_pos, off_aff, off_la, off_lb, off_spec, off_box, off_tab, off_rng, off_tmp;
   int bytes;
 };
 
@@ -114,6 +115,7 @@ __host__ __device__ inline GroupLayout make_layout(int nv_max, int G, int fp32) 
   L.off_box = o;  o = align16(o + (G / 8) * kBoxBytes);
   L.off_tab = o;  o = align16(o + (64 + 64 + 8) * real);
   L.off_rng = o;  o = align16(o + 2 * G * 8);
+  L.off_tmp = o;  o = align16(o + G * 8);
   L.bytes = o;
   return L;
 }
@@ -127,6 +129,9 @@ struct Schedule {
 // Launchers (return hipError_t).
 hipError_t launch_event_loop(const LoopArgs &a, int precision, int refresh_full,
                              const Schedule &s, hipStream_t stream);
+// Event loop with the learned barrier (one 64-lane group, binary32 rates).
+hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_species,
+                                 hipStream_t stream);
 size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision);
 hipError_t launch_queue_reset(int32_t *queue, hipStream_t stream);
 
@@ -135,5 +140,20 @@ hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h_desc, cons
                               void *rates, void *ea, hipStream_t stream);
 hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h_desc, const uint8_t *occ,
                             int precision, void *rates, void *ea, hipStream_t stream);
+
+// Surrogate (akmc_mlp.hip).
+hipError_t launch_env_encode(const LatDesc *d_desc, const uint8_t *occ, const int32_t *sites,
+                             int64_t n_sites, uint8_t *env, float *ea, hipStream_t stream);
+hipError_t launch_ood_fit(unsigned char *blob, const uint8_t *env, int64_t n, int S, hipStream_t stream);
+hipError_t launch_mlp_forward(const unsigned char *blob, int S, const uint8_t *env, int64_t n,
+                              float *ea, hipStream_t stream);
+hipError_t launch_mlp_init(unsigned char *blob, int S, uint64_t seed, hipStream_t stream);
+hipError_t launch_mlp_sync(unsigned char *blob, int S, hipStream_t stream);
+hipError_t launch_mlp_step(unsigned char *blob, int S, const uint8_t *env, const float *ea,
+                           int64_t n, int batch, int rows, int64_t start, uint64_t perm_key,
+                           int perm_bits, float *partial, int apply, float lr, float beta1,
+                           float beta2, float eps, float wd, int step, float *grad_out,
+                           float *loss_out, hipStream_t stream);
+size_t mlp_partial_bytes(int S, int batch);
 
 }  // namespace akmc

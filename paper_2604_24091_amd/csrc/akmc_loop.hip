@@ -27,6 +27,7 @@
 
 #include "akmc_device.hpp"
 #include "akmc_internal.hpp"
+#include "akmc_mlp.hpp"
 
 namespace akmc {
 
@@ -106,6 +107,7 @@ struct Lds {
   uint8_t *box;     // (G/8) footprint boxes
   Real *D1, *D2, *e0;
   double *ru1, *rw; // uniforms u1 and -ln u2 of the next G events
+  double *tmp;      // G values exchanged between the lanes of a group
 };
 
 template <class Real>
@@ -124,6 +126,7 @@ __device__ __forceinline__ Lds<Real> carve(unsigned char *base, const GroupLayou
   s.e0 = s.D2 + 64;
   s.ru1 = (double *)(base + L.off_rng);
   s.rw = s.ru1 + L.G;
+  s.tmp = (double *)(base + L.off_tmp);
   return s;
 }
 
@@ -157,7 +160,20 @@ __device__ __forceinline__ double eval_box(const uint8_t *box, int k, int S, con
   return (double)rate_from_barrier(ea, nu, kT);
 }
 
-template <int G, class Real>
+// LDS of the learned barrier (one group per block): bf16 weights, the
+// 64-row code staging, the activation staging tile, outputs, OOD bounds.
+struct MlpLds {
+  unsigned short *w1t, *w2t, *hst;
+  uint8_t *senv;
+  float *yb;
+  int *ood;
+};
+
+__host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
+  return (size_t)2 * kHid * mlp_k1(S) + (size_t)2 * kHid * kHid + 64 * 32 + 2 * 16 * kHid + 64 * 4 + 40 * 4;
+}
+
+template <int G, class Real, bool MLP = false>
 struct Runner {
   LoopArgs a;
   int qo1, qo2, qo3, qo4;   // level offsets in the tree region
@@ -168,11 +184,42 @@ struct Runner {
   int S, V, nv, nlev;
   Real nu, kT;
   uint8_t *occ;
+  // learned barrier
+  MlpLds ml;
+  MlpLayout mlay;
+  const float *prm;
+  float mu, sigma;
+  int k1;
+  int64_t n_ood;
 
   __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
                     const int (&foot_)[8], unsigned char *lds)
       : a(a_), gp(gp_) {
     s = carve<Real>(lds, L);
+    n_ood = 0;
+    if (MLP) {
+      const MlpHeader *hdr = (const MlpHeader *)a.mlp_blob;
+      const int Sm = hdr->S;
+      k1 = hdr->k1;
+      mlay = mlp_layout(Sm);
+      prm = (const float *)(a.mlp_blob + mlay.params);
+      mu = hdr->mu;
+      sigma = hdr->sigma;
+      unsigned char *b = lds + L.bytes;
+      ml.w1t = (unsigned short *)b;
+      ml.w2t = ml.w1t + kHid * k1;
+      ml.senv = (uint8_t *)(ml.w2t + kHid * kHid);
+      ml.hst = (unsigned short *)(ml.senv + 64 * 32);
+      ml.yb = (float *)(ml.hst + 16 * kHid);
+      ml.ood = (int *)(ml.yb + 64);
+      const unsigned char *src1 = a.mlp_blob + mlay.w1t, *src2 = a.mlp_blob + mlay.w2t;
+      for (int o = gp.gl * 16; o < 2 * kHid * k1; o += 64 * 16)
+        *(uint4 *)((unsigned char *)ml.w1t + o) = *(const uint4 *)(src1 + o);
+      for (int o = gp.gl * 16; o < 2 * kHid * kHid; o += 64 * 16)
+        *(uint4 *)((unsigned char *)ml.w2t + o) = *(const uint4 *)(src2 + o);
+      if (gp.gl < 40) ml.ood[gp.gl] = hdr->ood_valid ? hdr->ood_max[gp.gl >> 3][gp.gl & 7] : 64;
+      gsync();
+    }
     qo1 = L.qoff[1];
     qo2 = L.qoff[2];
     qo3 = L.qoff[3];
@@ -196,48 +243,143 @@ struct Runner {
     return Q(l - 1)[8 * u + cnt - 1];
   }
 
-  // Re-evaluates the slots aff[0..na).
-  __device__ void refresh(int na) {
+  // Inclusive left-to-right sums within each 8-lane subgroup: lane c of
+  // subgroup q returns x_0 + x_1 + ... + x_c of that subgroup's values.
+  __device__ __forceinline__ double subgroup_prefix(double x, int q, int c) {
+    s.tmp[gp.gl] = x;
+    gsync();
+    const double *t = s.tmp + (q << 3);
+    double acc = t[0];
+#pragma unroll
+    for (int m = 1; m < 8; ++m)
+      if (m <= c) acc = acc + t[m];
+    gsync();
+    return acc;
+  }
+
+  // Learned-barrier rates of one refresh pass (all 64 lanes take part in the
+  // matrix-core forward; lane q*8+k owns candidate k of pass slot q).
+  __device__ double eval_mlp_pass(int np, int q, int k, int p0, int &vv) {
+    const uint8_t *box = s.box + q * kBoxBytes;
+    int A = V;
+    bool ood = false;
+    float ea_pair = 0.f;
+    if (q < np) {
+      vv = s.aff[p0 + q];
+      const int flip = (~k) & 7;
+      const int jb = kBoxC + dir_sx(k) + 7 * dir_sy(k) + 49 * dir_sz(k);
+      A = box[jb];
+      uint8_t *row = ml.senv + gp.gl * 32;
+      row[0] = (uint8_t)A;
+      uint32_t c1i = 0, c1j = 0, c2i = 0, c2j = 0;
+#pragma unroll
+      for (int d2 = 0; d2 < 8; ++d2) {
+        const int qq = d2 ^ flip;
+        const int off = dir_sx(qq) + 7 * dir_sy(qq) + 49 * dir_sz(qq);
+        const uint8_t si = box[kBoxC + off], sj = box[jb + off];
+        if (d2 < 7) { row[1 + d2] = si; c1i += onehot(si); }
+        if (d2 > 0) { row[13 + d2] = sj; c1j += onehot(sj); }
+      }
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        const int axis = m >> 1;
+        const int mm = ((flip >> (2 - axis)) & 1) ? (m ^ 1) : m;
+        const int off = ((mm & 1) ? -1 : 1) * (axis == 0 ? 2 : axis == 1 ? 14 : 98);
+        const uint8_t si = box[kBoxC + off], sj = box[jb + off];
+        row[8 + m] = si;
+        row[21 + m] = sj;
+        c2i += onehot(si);
+        c2j += onehot(sj);
+      }
+      if (A != V) {
+        // N1(i) without j does not contain the moving atom's site; the box
+        // centre (the vacancy) is not part of N1(j) without i.
+        const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, s.D1 + A * S, s.D2 + A * S, S);
+        ea_pair = (float)(s.e0[A] + Real(0.5) * de);
+        ood = ml.ood[32 + A] < 1;  // moving species never seen in training
+        for (int sp = 0; sp < S; ++sp)
+          ood = ood || nib(c1i, sp) > ml.ood[sp] || nib(c2i, sp) > ml.ood[8 + sp] ||
+                nib(c1j, sp) > ml.ood[16 + sp] || nib(c2j, sp) > ml.ood[24 + sp];
+      }
+    }
+    gsync();
+    const int ntiles = (np * 8 + 15) / 16;
+    for (int t = 0; t < ntiles; ++t) {
+      unsigned short h1b[8][4], h2b[8][4];
+      float gp1[8][4], gp2[8][4], y[4];
+      mlp_fwd16<false>(ml.senv + t * 16 * 32, ml.w1t, ml.w2t, ml.hst, prm, mlay, S, k1, h1b, h2b,
+                       gp1, gp2, y);
+      if ((gp.gl & 15) == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ml.yb[t * 16 + 4 * (gp.gl >> 4) + i] = y[i];
+    }
+    gsync();
+    double r = 0.0;
+    const bool live = q < np && A != V;
+    if (q < np) s.spec[vv * 8 + k] = (uint8_t)A;
+    if (live) {
+      const float ea = ood ? ea_pair : mu + sigma * ml.yb[gp.gl];
+      r = (double)rate_from_barrier(ea, (float)nu, (float)kT);
+    }
+    n_ood += __popcll(gp.ballot(live && ood));
+    return r;
+  }
+
+  // Re-evaluates the slots aff[0..na).  The footprint gathers of the first
+  // pass are issued before this event's swap is stored (swap_lane0: lane 0
+  // then stores occ[si] = A_new and occ[sj] = V), and the two swapped sites
+  // are patched in the boxes, so the gathers never wait for the swap; the
+  // stores of earlier events were completed by the caller's fence.
+  __device__ void refresh(int na, int si, int sj, int a_new, bool swap_lane0,
+                          akmc_event *ev, const akmc_event &rec) {
     constexpr int P = G / 8;
     for (int p0 = 0; p0 < na; p0 += P) {
       const int np = min(P, na - p0);
+      int site[8];
+      uint8_t val[8];
 #pragma unroll
       for (int m = 0; m < 8; ++m) {
         const int f = foot[m];
-        if (f < 0) continue;
-        const int q = (f >> 18) & 63;
-        if (q >= np) continue;
-        const int bi = f & 511;
-        uint8_t val;
-        if (f & (1 << 24)) {
-          val = (uint8_t)V;
-        } else {
-          const int pp = s.pos[s.aff[p0 + q]];
-          const int X = wrapc(pos_x(pp) + ((f >> 9) & 7) - 3, g.X2);
-          const int Y = wrapc(pos_y(pp) + ((f >> 12) & 7) - 3, g.Y2);
-          const int Z = wrapc(pos_z(pp) + ((f >> 15) & 7) - 3, g.Z2);
-          val = occ[site_of(g, X, Y, Z)];
-        }
-        s.box[q * kBoxBytes + bi] = val;
+        site[m] = -1;
+        val[m] = (uint8_t)V;
+        if (f < 0 || ((f >> 18) & 63) >= np || (f & (1 << 24))) continue;
+        const int pp = s.pos[s.aff[p0 + ((f >> 18) & 63)]];
+        const int X = wrapc(pos_x(pp) + ((f >> 9) & 7) - 3, g.X2);
+        const int Y = wrapc(pos_y(pp) + ((f >> 12) & 7) - 3, g.Y2);
+        const int Z = wrapc(pos_z(pp) + ((f >> 15) & 7) - 3, g.Z2);
+        site[m] = site_of(g, X, Y, Z);
+        val[m] = occ[site[m]];
+      }
+      if (p0 == 0 && swap_lane0 && gp.gl == 0) {
+        occ[si] = (uint8_t)a_new;
+        occ[sj] = (uint8_t)V;
+        if (ev) *ev = rec;
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int f = foot[m];
+        if (f < 0 || ((f >> 18) & 63) >= np) continue;
+        uint8_t v8 = val[m];
+        if (site[m] == si) v8 = (uint8_t)a_new;
+        else if (site[m] == sj) v8 = (uint8_t)V;
+        s.box[((f >> 18) & 63) * kBoxBytes + (f & 511)] = v8;
       }
       gsync();
       const int q = gp.gl >> 3, k = gp.gl & 7;
       double r = 0.0;
-      int vv = -1;
-      if (q < np) {
-        vv = s.aff[p0 + q];
-        int A;
-        r = eval_box<Real>(s.box + q * kBoxBytes, k, S, s.D1, s.D2, s.e0, nu, kT, A);
-        s.spec[vv * 8 + k] = (uint8_t)A;
+      int vv = 0;
+      if (!MLP) {
+        if (q < np) {
+          vv = s.aff[p0 + q];
+          int A;
+          r = eval_box<Real>(s.box + q * kBoxBytes, k, S, s.D1, s.D2, s.e0, nu, kT, A);
+          s.spec[vv * 8 + k] = (uint8_t)A;
+        }
+      } else {
+        r = eval_mlp_pass(np, q, k, p0, vv);
       }
-      // Partial sums over directions: part[v][k] = r0 + r1 + ... + rk.
-      double acc = 0.0;
-#pragma unroll
-      for (int mm = 0; mm < 8; ++mm) {
-        const double x = __shfl(r, gp.base + (q << 3) + mm, 64);
-        if (mm == 0) acc = x;
-        else if (mm <= k) acc = acc + x;
-      }
+      // part[v][k] = r0 + r1 + ... + rk
+      const double acc = subgroup_prefix(r, q, k);
       if (q < np) s.part[vv * 8 + k] = acc;
       gsync();
     }
@@ -275,13 +417,7 @@ struct Runner {
         cnt = min(8, nl(l) - base);
         if (c < cnt) x = node_value(l, base + c);
       }
-      double acc = 0.0;
-#pragma unroll
-      for (int mm = 0; mm < 8; ++mm) {
-        const double y = __shfl(x, gp.base + (q << 3) + mm, 64);
-        if (mm == 0) acc = y;
-        else if (mm <= c) acc = acc + y;
-      }
+      const double acc = subgroup_prefix(x, q, c);
       if (live && c < cnt) Q(l)[base + c] = acc;
       gsync();
     }
@@ -339,7 +475,8 @@ struct Runner {
       s.aff[v] = v;
     }
     gsync();
-    refresh(nv);
+    akmc_event none{};
+    refresh(nv, -1, -1, 0, false, nullptr, none);
     update_tree(nv);
     double gtot = gamma_tot();
     frozen = !(gtot > 0.0);
@@ -396,33 +533,23 @@ struct Runner {
                 JZ = wrapc(Z + dir_sz(k), g.Z2);
       const int si = site_of(g, X, Y, Z), sj = site_of(g, JX, JY, JZ);
       const double dt = time_mode ? 1.0 / gtot : w / gtot;
+      akmc_event rec;
+      rec.n = n;
+      rec.slot = v;
+      rec.from_site = si;
+      rec.to_site = sj;
+      rec.dir = (uint8_t)k;
+      rec.species = (uint8_t)A;
+      rec.pad[0] = 0;
+      rec.pad[1] = 0;
+      rec.gamma_tot = gtot;
+      rec.dt = dt;
+      akmc_event *ev = evlog ? evlog + e : nullptr;
       gsync();
-      if (gl == 0) {
-        if (evlog) {
-          akmc_event *ev = evlog + e;
-          ev->n = n;
-          ev->slot = v;
-          ev->from_site = si;
-          ev->to_site = sj;
-          ev->dir = (uint8_t)k;
-          ev->species = (uint8_t)A;
-          ev->pad[0] = 0;
-          ev->pad[1] = 0;
-          ev->gamma_tot = gtot;
-          ev->dt = dt;
-        }
-        occ[si] = (uint8_t)A;
-        occ[sj] = (uint8_t)V;
-        s.pos[v] = pack_pos(JX, JY, JZ);
-      }
-      t += dt;
-      dig = fnv_event(dig, n, si, sj);
-      n += 1;
-      // The swap's stores must be visible to the gathers below.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (gl == 0) s.pos[v] = pack_pos(JX, JY, JZ);
       gsync();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
+      // Slots whose footprint may contain i or j.
       int na;
       if (full) {
         na = nv;
@@ -445,7 +572,12 @@ struct Runner {
         }
         gsync();
       }
-      refresh(na);
+      t += dt;
+      dig = fnv_event(dig, n, si, sj);
+      n += 1;
+      // Occupancy stores of earlier events complete before the gathers.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      refresh(na, si, sj, A, true, ev, rec);
       update_tree(na);
       gtot = gamma_tot();
       frozen = !(gtot > 0.0);
@@ -461,12 +593,13 @@ struct Runner {
       st->digest = dig;
       st->gamma_tot = gtot;
       st->frozen = frozen;
+      st->n_ood += n_ood;
     }
     gsync();
   }
 };
 
-template <int G, int WAVES, bool FP32>
+template <int G, int WAVES, bool FP32, bool MLP = false>
 __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayout L) {
   using Real = typename std::conditional<FP32, float, double>::type;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -500,7 +633,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayo
     }
   }
 
-  Runner<G, Real> run(a, L, gp, foot, mine);
+  Runner<G, Real, MLP> run(a, L, gp, foot, mine);
   for (;;) {
     int idx = 0;
     if (gp.gl == 0) idx = atomicAdd(a.queue, 1);
@@ -557,6 +690,21 @@ static hipError_t launch_g(const LoopArgs &a, const Schedule &s, hipStream_t str
     case 32: return launch_w<32, FP32>(a, s, stream);
     default: return launch_w<64, FP32>(a, s, stream);
   }
+}
+
+hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_species,
+                                 hipStream_t stream) {
+  LoopArgs b = a;
+  b.refresh_full = refresh_full;
+  hipError_t e = launch_queue_reset(a.queue, stream);
+  if (e != hipSuccess) return e;
+  const GroupLayout L = make_layout(a.nv_max, 64, 1);
+  const size_t lds = (size_t)L.bytes + mlp_loop_lds_bytes(n_species);
+  auto kern = k_event_loop<64, 1, true, true>;
+  e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(1), dim3(64), lds, stream, b, L);
+  return hipGetLastError();
 }
 
 hipError_t launch_event_loop(const LoopArgs &a, int precision, int refresh_full,

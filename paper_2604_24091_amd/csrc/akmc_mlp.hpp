@@ -1,0 +1,194 @@
+// Learned barrier surrogate: layout of the weight blob and the device
+// forward pass shared by the bulk inference, training and event-loop
+// kernels.
+//
+// Network (per candidate): 27 footprint slots in the jump frame, one-hot
+// over S species, zero-padded to K1 = 32*ceil(27*S/32) inputs;
+//   h1 = gelu(x W1 + b1), h2 = gelu(h1 W2 + b2), y = h2 . w3 + b3,
+//   Ea = mu + sigma*y,   gelu(z) = z/2 (1 + tanh(sqrt(2/pi)(z + 0.044715 z^3))).
+// Weights and activations are bfloat16 on the matrix cores with binary32
+// accumulation; biases, the output layer sum and the optimiser state are
+// binary32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace akmc {
+
+constexpr int kHid = 128;
+constexpr int kSlots = 27;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline int mlp_k1(int S) { return 32 * ((kSlots * S + 31) / 32); }
+__host__ __device__ inline int mlp_nparams(int S) {
+  const int k1 = mlp_k1(S);
+  return k1 * kHid + kHid + kHid * kHid + kHid + kHid + 1;
+}
+
+// Header at the start of the blob.
+struct MlpHeader {
+  int32_t S, k1, nparams, step;
+  float mu, sigma;
+  int32_t ood_valid;
+  int32_t pad_;
+  int32_t ood_max[5][8];  // largest per-species count seen in training: 4 bond groups, then the moving species
+};
+
+// Byte offsets inside the blob; every segment 256-byte aligned.
+struct MlpLayout {
+  size_t hdr, params, m, v, w1t, w2t, w2r, total;
+  // element offsets inside the parameter vector
+  int oW1, ob1, oW2, ob2, ow3, ob3;
+};
+
+__host__ __device__ inline size_t mlp_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+__host__ __device__ inline MlpLayout mlp_layout(int S) {
+  MlpLayout L;
+  const int k1 = mlp_k1(S), np = mlp_nparams(S);
+  size_t o = 0;
+  L.hdr = o;    o += mlp_up(sizeof(MlpHeader));
+  L.params = o; o += mlp_up(sizeof(float) * (size_t)np);
+  L.m = o;      o += mlp_up(sizeof(float) * (size_t)np);
+  L.v = o;      o += mlp_up(sizeof(float) * (size_t)np);
+  L.w1t = o;    o += mlp_up(2 * (size_t)kHid * k1);
+  L.w2t = o;    o += mlp_up(2 * (size_t)kHid * kHid);
+  L.w2r = o;    o += mlp_up(2 * (size_t)kHid * kHid);
+  L.total = o;
+  L.oW1 = 0;
+  L.ob1 = L.oW1 + k1 * kHid;
+  L.oW2 = L.ob1 + kHid;
+  L.ob2 = L.oW2 + kHid * kHid;
+  L.ow3 = L.ob2 + kHid;
+  L.ob3 = L.ow3 + kHid;
+  return L;
+}
+
+// slot = f / S for 0 <= f < 224 and 2 <= S <= 8: f * ceil(2^16/S) >> 16 is
+// exact there (the rounding excess stays below 224/2^16 < 1/S).
+__device__ __forceinline__ int div_s(int f, int magic) { return (f * magic) >> 16; }
+__host__ __device__ inline int s_magic(int S) { return (65536 + S - 1) / S; }
+
+__device__ __forceinline__ unsigned short f2bf(float f) {
+  // round to nearest even (finite values)
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) {
+  return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
+__device__ __forceinline__ float gelu_f(float z) {
+  const float c = 0.7978845608028654f;  // sqrt(2/pi)
+  const float u = c * (z + 0.044715f * z * z * z);
+  return 0.5f * z * (1.0f + tanhf(u));
+}
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  const float c = 0.7978845608028654f;
+  const float u = c * (z + 0.044715f * z * z * z);
+  const float t = tanhf(u);
+  return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * z * z);
+}
+
+// Forward pass of 16 rows by one wavefront.
+//   env:   LDS, 16 rows x 32 bytes of species codes (27 used)
+//   w1t:   LDS, bf16 [128][k1]   (output feature major)
+//   w2t:   LDS, bf16 [128][128]
+//   hst:   LDS, bf16 [16][128] staging of one activation tile
+//   prm:   binary32 parameter vector (biases, w3, b3)
+// Results per lane (C layout of the 16x16 matrix-core tiles: lane l holds
+// rows 4*(l/16)+i, column 16*c + l%16 of tile c):
+//   h1b[c][i], h2b[c][i]  bf16 activations; gp1/gp2 gelu'(z) (if GRAD);
+//   y[i] for rows 4*(l/16)+i (sum over all columns, identical in the 16
+//   lanes of a row group).
+template <bool GRAD>
+__device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned short *w1t,
+                                          const unsigned short *w2t, unsigned short *hst,
+                                          const float *prm, const MlpLayout &L, int S, int k1,
+                                          unsigned short (&h1b)[8][4], unsigned short (&h2b)[8][4],
+                                          float (&gp1)[8][4], float (&gp2)[8][4], float (&y)[4]) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, q = l >> 4;
+  // Layer 1: A from the one-hot codes (row r, features 32t + 8q .. +7).
+  f32x4 acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int nk = k1 / 32;
+  const int mg = s_magic(S);
+  for (int t = 0; t < nk; ++t) {
+    bf16x8 a;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int f = 32 * t + 8 * q + i;
+      const int slot = div_s(f, mg), sp = f - slot * S;
+      const bool one = slot < kSlots && env[r * 32 + slot] == sp;
+      a[i] = __builtin_bit_cast(__bf16, (unsigned short)(one ? 0x3F80 : 0));
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const bf16x8 b = *(const bf16x8 *)(w1t + (16 * c + r) * k1 + 32 * t + 8 * q);
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const float bias = prm[L.ob1 + 16 * c + r];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float z = acc[c][i] + bias;
+      const unsigned short hb = f2bf(gelu_f(z));
+      h1b[c][i] = hb;
+      if (GRAD) gp1[c][i] = gelu_grad_f(z);
+      hst[(4 * q + i) * kHid + 16 * c + r] = hb;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  // Layer 2: A = h1 rows from the staging tile.
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const bf16x8 a = *(const bf16x8 *)(hst + r * kHid + 32 * t + 8 * q);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const bf16x8 b = *(const bf16x8 *)(w2t + (16 * c + r) * kHid + 32 * t + 8 * q);
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+    }
+  }
+  float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const float bias = prm[L.ob2 + 16 * c + r];
+    const float w3 = bf2f(f2bf(prm[L.ow3 + 16 * c + r]));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float z = acc[c][i] + bias;
+      const unsigned short hb = f2bf(gelu_f(z));
+      h2b[c][i] = hb;
+      if (GRAD) gp2[c][i] = gelu_grad_f(z);
+      part[i] = fmaf(bf2f(hb), w3, part[i]);
+    }
+  }
+  // Sum the 16 lanes of each row group (lanes 16q .. 16q+15).
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float v = part[i];
+    v += __shfl_xor(v, 8, 16);
+    v += __shfl_xor(v, 4, 16);
+    v += __shfl_xor(v, 2, 16);
+    v += __shfl_xor(v, 1, 16);
+    y[i] = v + prm[L.ob3];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+}  // namespace akmc

@@ -114,27 +114,61 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
 
 // ---------------------------------------------------------- bulk sweep
 
+template <class Real> struct Sweep;
+template <> struct Sweep<double> {
+  // ln r = Cn[A][s_p] + (beta/2) dG;  r = exp(ln r)
+  __device__ static double C(const LatDesc *d, int i) { return d->Cn[i]; }
+  __device__ static double h(const LatDesc *d) { return d->half_beta; }
+  __device__ static double rate(double c, double h, double dg) { return exp(fma(h, dg, c)); }
+};
+template <> struct Sweep<float> {
+  // log2 r = C2f[A][s_p] + h2f dG;  r = 2^(log2 r), one hardware exponential
+  __device__ static float C(const LatDesc *d, int i) { return d->C2f[i]; }
+  __device__ static float h(const LatDesc *d) { return d->h2f; }
+  __device__ static float rate(float c, float h, float dg) {
+    return __builtin_amdgcn_exp2f(fmaf(h, dg, c));
+  }
+};
+
+constexpr int kSweepThreads = 256;
+
+template <int TX, int TY, int TZ>
+struct SweepShape {
+  static constexpr int EX = TX + 4, EY = TY + 4, EZ = TZ + 4, EV = EX * EY * EZ;  // occupancy brick
+  static constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, HV = HX * HY * HZ;  // field region
+  static constexpr int NT = 2 * TX * TY * TZ;                                     // brick sites
+  static constexpr int OCC_BYTES = (2 * EV + 15) & ~15;
+  static size_t lds_bytes(int S, size_t real) {
+    return OCC_BYTES + (size_t)2 * HV * (size_t)(S - 1) * real;
+  }
+};
+
+// Region layout of the field G'_A: corners (b = 0) at cells [0, T+1) and
+// centres (b = 1) at cells [-1, T) of the brick, each stored at index
+// h = c + b.  The targets of a corner at cell c are the centres at cells
+// c - 1 + [s > 0], those of a centre the corners at c + [s > 0]; both sit
+// at index h = c + [s > 0] of the other sublattice.
 template <int TX, int TY, int TZ, class Real, bool WITH_EA>
-__global__ __launch_bounds__(256) void k_rates_all(const LatDesc *__restrict__ d,
-                                                   const uint8_t *__restrict__ occ,
-                                                   Real *__restrict__ rates,
-                                                   Real *__restrict__ ea) {
-  constexpr int EX = TX + 4, EY = TY + 4, EZ = TZ + 4, EV = EX * EY * EZ;  // occupancy brick
-  constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, HV = HX * HY * HZ;  // target field
-  constexpr int NT = 2 * TX * TY * TZ;                                     // brick sites
-  constexpr int EVP = (2 * EV + 15) & ~15;
-  __shared__ __align__(16) uint8_t socc[EVP];
-  __shared__ Real sH[2 * HV];
-  __shared__ Real sG[256 * 8];
-  __shared__ Real sDs1[64], sDs2[64], sK[64], se0[8];
+__global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__restrict__ d,
+                                                             const uint8_t *__restrict__ occ,
+                                                             Real *__restrict__ rates,
+                                                             Real *__restrict__ ea) {
+  using Sh = SweepShape<TX, TY, TZ>;
+  constexpr int EX = Sh::EX, EY = Sh::EY, EV = Sh::EV;
+  constexpr int HX = Sh::HX, HY = Sh::HY, HV = Sh::HV;
+  extern __shared__ __align__(16) unsigned char sweep_lds[];
+  uint8_t *socc = sweep_lds;
+  Real *sG = (Real *)(sweep_lds + Sh::OCC_BYTES);
+  __shared__ Real sDs1[64], sDs2[64], sC[64], sK[64], se0[8];
 
   const int tid = threadIdx.x;
   const int lx = d->lx, ly = d->ly, lz = d->lz;
-  const int S = d->S, V = S - 1;
+  const int S = d->S, V = S - 1, NA = S - 1;
   const int ncell = lx * ly * lz;
   if (tid < 64) {
     sDs1[tid] = Tab<Real>::Ds1(d)[tid];
     sDs2[tid] = Tab<Real>::Ds2(d)[tid];
+    sC[tid] = Sweep<Real>::C(d, tid);
     sK[tid] = Tab<Real>::K(d)[tid];
   }
   if (tid < 8) se0[tid] = Tab<Real>::e0(d)[tid];
@@ -145,18 +179,27 @@ __global__ __launch_bounds__(256) void k_rates_all(const LatDesc *__restrict__ d
   const int y0 = ((tile / ntx) % nty) * TY;
   const int z0 = (tile / (ntx * nty)) * TZ;
 
-  // Phase 1: occupancy brick, cells [-2, T+2) of both sublattices.
-  for (int r = tid; r < 2 * EV; r += 256) {
-    const int b = r / EV;
-    int q = r - b * EV;
-    const int ex = q % EX;
-    q /= EX;
-    const int ey = q % EY;
-    const int ez = q / EY;
+  // Phase 1: occupancy brick, cells [-2, T+2) of both sublattices, x fastest
+  // across lanes.  One conditional wrap suffices when every edge exceeds
+  // the brick; smaller lattices take the general modulo.
+  const bool simple = lx > TX + 2 && ly > TY + 2 && lz > TZ + 2;
+  for (int r = tid; r < 2 * EV; r += kSweepThreads) {
+    const int ex = r % EX;
+    const int row = r / EX;
+    const int ey = row % EY;
+    const int bz = row / EY;
+    const int ez = bz % Sh::EZ;
+    const int b = bz / Sh::EZ;
     int gx = x0 + ex - 2, gy = y0 + ey - 2, gz = z0 + ez - 2;
-    gx = ((gx % lx) + lx) % lx;
-    gy = ((gy % ly) + ly) % ly;
-    gz = ((gz % lz) + lz) % lz;
+    if (simple) {
+      gx += gx < 0 ? lx : 0;  gx -= gx >= lx ? lx : 0;
+      gy += gy < 0 ? ly : 0;  gy -= gy >= ly ? ly : 0;
+      gz += gz < 0 ? lz : 0;  gz -= gz >= lz ? lz : 0;
+    } else {
+      gx = ((gx % lx) + lx) % lx;
+      gy = ((gy % ly) + ly) % ly;
+      gz = ((gz % lz) + lz) % lz;
+    }
     socc[r] = occ[b * ncell + (gz * ly + gy) * lx + gx];
   }
   __syncthreads();
@@ -164,81 +207,71 @@ __global__ __launch_bounds__(256) void k_rates_all(const LatDesc *__restrict__ d
   auto oidx = [&](int b, int cx, int cy, int cz) {
     return b * EV + ((cz + 2) * EY + (cy + 2)) * EX + (cx + 2);
   };
-  // Bond counts of site (b, c) from the brick.
-  auto counts = [&](int b, int cx, int cy, int cz, uint32_t &c1, uint32_t &c2) {
-    const int o = b ? 0 : -1;  // first neighbours of a corner sit in cells c-1..c, of a centre in c..c+1
-    c1 = 0;
+
+  // Phase 2: G'_A(q) for every mover species A at every region site:
+  //   G'_A(q) = sum_s n1_s(q) Ds1[A][s] + n2_s(q) Ds2[A][s]   (s = 0 drops out)
+  for (int r = tid; r < 2 * HV; r += kSweepThreads) {
+    const int hx = r % HX;
+    const int row = r / HX;
+    const int hy = row % HY;
+    const int bz = row / HY;
+    const int hz = bz % Sh::HZ;
+    const int b = bz / Sh::HZ;
+    const int cx = hx - b, cy = hy - b, cz = hz - b;
+    const int o = b ? 0 : -1;  // first shell of a corner: cells c-1..c; of a centre: c..c+1
+    uint32_t c1 = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q)
       c1 += onehot(socc[oidx(1 - b, cx + o + ((q >> 2) & 1), cy + o + ((q >> 1) & 1), cz + o + (q & 1))]);
-    c2 = onehot(socc[oidx(b, cx + 1, cy, cz)]) + onehot(socc[oidx(b, cx - 1, cy, cz)]) +
-         onehot(socc[oidx(b, cx, cy + 1, cz)]) + onehot(socc[oidx(b, cx, cy - 1, cz)]) +
-         onehot(socc[oidx(b, cx, cy, cz + 1)]) + onehot(socc[oidx(b, cx, cy, cz - 1)]);
-  };
-
-  // Phase 2: H(q) for every possible target: corners at cells [0, T+1),
-  // centres at cells [-1, T) (stored shifted by one cell).
-  for (int r = tid; r < 2 * HV; r += 256) {
-    const int b = r / HV;
-    int q = r - b * HV;
-    const int hx = q % HX;
-    q /= HX;
-    const int hy = q % HY;
-    const int hz = q / HY;
-    const int cx = hx - b, cy = hy - b, cz = hz - b;
-    const int sq = socc[oidx(b, cx, cy, cz)];
-    Real h = Real(0);
-    if (sq != V) {
-      uint32_t c1, c2;
-      counts(b, cx, cy, cz, c1, c2);
-      for (int s = 1; s < S; ++s) {
-        h = fma((Real)nib(c1, s), sDs1[sq * S + s], h);
-        h = fma((Real)nib(c2, s), sDs2[sq * S + s], h);
-      }
+    const uint32_t c2 =
+        onehot(socc[oidx(b, cx + 1, cy, cz)]) + onehot(socc[oidx(b, cx - 1, cy, cz)]) +
+        onehot(socc[oidx(b, cx, cy + 1, cz)]) + onehot(socc[oidx(b, cx, cy - 1, cz)]) +
+        onehot(socc[oidx(b, cx, cy, cz + 1)]) + onehot(socc[oidx(b, cx, cy, cz - 1)]);
+    Real g[8];
+#pragma unroll
+    for (int A = 0; A < 8; ++A) g[A] = Real(0);
+    for (int s = 1; s < S; ++s) {
+      const Real n1 = (Real)nib(c1, s), n2 = (Real)nib(c2, s);
+#pragma unroll
+      for (int A = 0; A < 8; ++A)
+        if (A < NA) g[A] = fma(n2, sDs2[A * S + s], fma(n1, sDs1[A * S + s], g[A]));
     }
-    sH[r] = h;
+#pragma unroll
+    for (int A = 0; A < 8; ++A)
+      if (A < NA) sG[A * (2 * HV) + r] = g[A];
   }
   __syncthreads();
 
-  // Phase 3: the 8 candidates of every brick site.
-  const Real nu = Tab<Real>::nu(d), beta = Tab<Real>::beta(d);
-  Real *myG = sG + tid * 8;
-  for (int t = tid; t < NT; t += 256) {
-    const int b = t / (TX * TY * TZ);
-    int q = t - b * (TX * TY * TZ);
-    const int cx = q % TX;
-    q /= TX;
-    const int cy = q % TY;
-    const int cz = q / TY;
+  // Phase 3: the 8 candidates of every brick site, from the field alone.
+  const Real h = Sweep<Real>::h(d);
+  for (int t = tid; t < Sh::NT; t += kSweepThreads) {
+    const int cx = t % TX;
+    const int row = t / TX;
+    const int cy = row % TY;
+    const int bz = row / TY;
+    const int cz = bz % TZ;
+    const int b = bz / TZ;
     const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
     if (gx >= lx || gy >= ly || gz >= lz) continue;
     const int sp = socc[oidx(b, cx, cy, cz)];
-    uint32_t c1, c2;
-    counts(b, cx, cy, cz, c1, c2);
-    for (int A = 0; A < V; ++A) {
-      Real g = Real(0);
-      for (int s = 1; s < S; ++s) {
-        g = fma((Real)nib(c1, s), sDs1[A * S + s], g);
-        g = fma((Real)nib(c2, s), sDs2[A * S + s], g);
-      }
-      myG[A] = g;
-    }
+    // Field planes are species-major (plane A holds G'_A of every region
+    // site), so neighbouring lanes read neighbouring words.
+    const int ip = b * HV + ((cz + b) * HY + (cy + b)) * HX + (cx + b);
+    const int ij0 = (1 - b) * HV + (cz * HY + cy) * HX + cx;
     const int o = b ? 0 : -1;
     Real rr[8], ee[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int px = (k >> 2) & 1, py = (k >> 1) & 1, pz = k & 1;
       const int A = socc[oidx(1 - b, cx + o + px, cy + o + py, cz + o + pz)];
-      // Target j sits in the other sublattice's field at shifted cell c + [s > 0].
-      const Real hj = sH[(1 - b) * HV + ((cz + pz) * HY + (cy + py)) * HX + (cx + px)];
       if (A == V) {
         rr[k] = Real(0);
         ee[k] = inf_of<Real>();
       } else {
-        const Real de = (myG[A] - hj) + sK[A * S + sp];
-        const Real e = se0[A] + Real(0.5) * de;
-        ee[k] = e;
-        rr[k] = nu * exp(-(e * beta));
+        const Real gpa = sG[A * (2 * HV) + ip];
+        const Real gja = sG[A * (2 * HV) + ij0 + (pz * HY + py) * HX + px];
+        rr[k] = Sweep<Real>::rate(sC[A * S + sp], h, gja - gpa);
+        if (WITH_EA) ee[k] = se0[A] + Real(0.5) * ((gpa - gja) + sK[A * S + sp]);
       }
     }
     const int64_t site = (int64_t)b * ncell + ((int64_t)gz * ly + gy) * lx + gx;
@@ -270,27 +303,40 @@ hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h, const uin
   return hipGetLastError();
 }
 
-hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
-                            int precision, void *rates, void *ea, hipStream_t stream) {
-  constexpr int TX = 32, TY = 4, TZ = 4;
+template <int TX, int TY, int TZ, class Real>
+static hipError_t launch_sweep(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
+                               void *rates, void *ea, hipStream_t stream) {
+  using Sh = SweepShape<TX, TY, TZ>;
   const unsigned tiles = (unsigned)(((h.lx + TX - 1) / TX) * ((h.ly + TY - 1) / TY) *
                                     ((h.lz + TZ - 1) / TZ));
-  if (precision == AKMC_FP32) {
-    if (ea)
-      hipLaunchKernelGGL((k_rates_all<TX, TY, TZ, float, true>), dim3(tiles), dim3(256), 0,
-                         stream, d_desc, occ, (float *)rates, (float *)ea);
-    else
-      hipLaunchKernelGGL((k_rates_all<TX, TY, TZ, float, false>), dim3(tiles), dim3(256), 0,
-                         stream, d_desc, occ, (float *)rates, (float *)ea);
+  const size_t lds = Sh::lds_bytes(h.S, sizeof(Real));
+  if (ea) {
+    auto k = k_rates_all<TX, TY, TZ, Real, true>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3(tiles), dim3(kSweepThreads), lds, stream, d_desc, occ, (Real *)rates, (Real *)ea);
   } else {
-    if (ea)
-      hipLaunchKernelGGL((k_rates_all<TX, TY, TZ, double, true>), dim3(tiles), dim3(256), 0,
-                         stream, d_desc, occ, (double *)rates, (double *)ea);
-    else
-      hipLaunchKernelGGL((k_rates_all<TX, TY, TZ, double, false>), dim3(tiles), dim3(256), 0,
-                         stream, d_desc, occ, (double *)rates, (double *)ea);
+    auto k = k_rates_all<TX, TY, TZ, Real, false>;
+    if (lds > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3(tiles), dim3(kSweepThreads), lds, stream, d_desc, occ, (Real *)rates, (Real *)ea);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
+                            int precision, void *rates, void *ea, hipStream_t stream) {
+  // The field holds S-1 values per region site: narrow the brick for many species.
+  if (h.S <= 5) {
+    if (precision == AKMC_FP32) return launch_sweep<32, 4, 4, float>(d_desc, h, occ, rates, ea, stream);
+    return launch_sweep<32, 4, 4, double>(d_desc, h, occ, rates, ea, stream);
+  }
+  if (precision == AKMC_FP32) return launch_sweep<16, 4, 4, float>(d_desc, h, occ, rates, ea, stream);
+  return launch_sweep<16, 4, 4, double>(d_desc, h, occ, rates, ea, stream);
 }
 
 }  // namespace akmc

@@ -1,0 +1,283 @@
+"""GPU parity of the learned barrier surrogate (akmc_env_encode, akmc_mlp_*).
+
+Tolerances:
+  encoding      bit-exact species codes; pair barrier within 1e-6 relative
+                (binary32 output of a binary64 computation);
+  forward       against the oracle evaluated with the same bfloat16
+                roundings (weights, h1, h2): 2e-3 eV absolute.  The two sides
+                differ only in binary32 vs binary64 accumulation, which can
+                move a hidden unit across a bfloat16 rounding boundary; one
+                such flip changes y by |w3_i| * 2^-8 |h2_i| (about 1e-3 in
+                sigma units at these scales);
+  gradients     relative L2 error <= 2e-2 per parameter block against the
+                binary64 oracle with the same roundings;
+  AdamW         one update from the GPU's own gradient: binary32 against the
+                binary64 formula, 1e-6 relative to the step size.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_24091_amd import akmc
+from paper_2604_24091_amd import workloads as W
+from tests.gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+S = 5
+
+
+def _blob(torch):
+    return torch.empty(akmc.mlp_blob_bytes(S), dtype=torch.uint8, device="cuda")
+
+
+def _dataset(oracle_mod, n_sites=3000, seed=3, solute=0.3):
+    """Encoded candidates of random probe sites of a heavily alloyed lattice
+    and their oracle barriers (admissible jumps only)."""
+    rng = np.random.default_rng(seed)
+    spec = W.random_lattice(rng, (12, 12, 12), S, 40, solute_total=solute)
+    o = oracle_mod.Oracle(spec)
+    sites = rng.choice(spec.n_sites, n_sites, replace=False).astype(np.int32)
+    _, ea = o.rates_sites(sites)
+    env = np.array([[o.encode_env(int(i), k) for k in range(8)] for i in sites], dtype=np.uint8)
+    return spec, sites, env, ea
+
+
+def test_env_encode_matches_oracle(oracle_mod):
+    import torch
+    banner("mlp env encode")
+    spec, sites, env_ref, ea_ref = _dataset(oracle_mod, n_sites=2000)
+    lat = akmc.Lattice(spec)
+    d_sites = torch.as_tensor(sites, device="cuda")
+    env = torch.empty((len(sites), 8, 27), dtype=torch.uint8, device="cuda")
+    ea = torch.empty((len(sites), 8), dtype=torch.float32, device="cuda")
+    akmc.env_encode(lat.h, akmc.RATES_SITES, d_sites, len(sites), env, ea)
+    torch.cuda.synchronize()
+    lat.close()
+    assert np.array_equal(env.cpu().numpy(), env_ref)
+    e = ea.cpu().numpy().astype(np.float64)
+    m = np.isfinite(ea_ref)
+    assert np.array_equal(np.isfinite(e), m)
+    assert np.max(np.abs(e[m] - ea_ref[m]) / np.abs(ea_ref[m])) <= 1e-6
+
+
+def _random_params(rng, scale=1.0):
+    from oracle import mlp as M
+    p = M.init_params(S, rng, mu=0.64, sigma=0.09)
+    for k in M.PARAM_KEYS:
+        p[k] = p[k] * scale + rng.normal(scale=0.02, size=np.shape(p[k]))
+    return p
+
+
+def _rows(env, ea):
+    e = env.reshape(-1, 27)
+    a = ea.reshape(-1)
+    keep = np.isfinite(a)
+    return np.ascontiguousarray(e[keep]), np.ascontiguousarray(a[keep])
+
+
+def test_forward_matches_oracle(oracle_mod):
+    import torch
+    from oracle import mlp as M
+    banner("mlp forward")
+    rng = np.random.default_rng(5)
+    _, _, env, ea = _dataset(oracle_mod, n_sites=1500, seed=5)
+    env, ea = _rows(env, ea)
+    p = _random_params(rng)
+    # Parameters go through binary32 on their way to the GPU.
+    p32 = {k: (np.asarray(p[k], np.float32).astype(np.float64) if k in M.PARAM_KEYS else p[k]) for k in p}
+    blob = _blob(torch)
+    akmc.mlp_set_params(blob, S, akmc.pack_params(p32), p["mu"], p["sigma"])
+    d_env = torch.as_tensor(env, device="cuda")
+    out = torch.empty(len(env), dtype=torch.float32, device="cuda")
+    for n in (len(env), 1, 17, 1000):          # ragged tails of the 16-row tiles
+        akmc.mlp_forward(blob, S, d_env, n, out)
+        torch.cuda.synchronize()
+        got = out[:n].cpu().numpy().astype(np.float64)
+        ref = M.predict_ea(p32, env[:n], S, bf16_act=True)
+        assert np.max(np.abs(got - ref)) <= 2e-3, np.max(np.abs(got - ref))
+        assert np.median(np.abs(got - ref)) <= 1e-4
+    params, mu, sigma = akmc.mlp_get_params(blob, S)
+    assert np.array_equal(params, akmc.pack_params(p32)) and mu == np.float32(p["mu"])
+
+
+def test_gradients_match_oracle(oracle_mod):
+    import torch
+    from oracle import mlp as M
+    banner("mlp gradients")
+    rng = np.random.default_rng(6)
+    _, _, env, ea = _dataset(oracle_mod, n_sites=300, seed=6)
+    env, ea = _rows(env, ea)
+    p = _random_params(rng)
+    p32 = {k: (np.asarray(p[k], np.float32).astype(np.float64) if k in M.PARAM_KEYS else p[k]) for k in p}
+    blob = _blob(torch)
+    akmc.mlp_set_params(blob, S, akmc.pack_params(p32), p["mu"], p["sigma"])
+    for n in (256, 200, 16, 37):
+        e, a = env[:n], ea[:n]
+        work = torch.empty(akmc.mlp_train_workspace_bytes(S, (n + 15) // 16 * 16), dtype=torch.uint8, device="cuda")
+        g = torch.empty(akmc.mlp_param_count(S), dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        akmc.mlp_grad(blob, S, torch.as_tensor(e, device="cuda"), torch.as_tensor(a.astype(np.float32), device="cuda"),
+                      n, g, work, loss)
+        torch.cuda.synchronize()
+        gg = akmc.unpack_params(g.cpu().numpy(), S)
+        lref, gref = M.loss_and_grads(p32, M.one_hot(e, S), a.astype(np.float32).astype(np.float64), bf16_act=True)
+        assert abs(float(loss.item()) - lref) <= 2e-2 * lref
+        for k in M.PARAM_KEYS:
+            num = np.linalg.norm(gg[k] - gref[k])
+            den = np.linalg.norm(gref[k])
+            assert num <= 2e-2 * den + 1e-7, (n, k, num / max(den, 1e-30))
+
+
+def test_adamw_step_matches_oracle(oracle_mod):
+    import torch
+    from oracle import mlp as M
+    banner("mlp adamw")
+    rng = np.random.default_rng(7)
+    _, _, env, ea = _dataset(oracle_mod, n_sites=200, seed=7)
+    env, ea = _rows(env, ea)
+    n = 256
+    env, ea = env[:n], ea[:n].astype(np.float32)
+    p = _random_params(rng)
+    p32 = {k: (np.asarray(p[k], np.float32).astype(np.float64) if k in M.PARAM_KEYS else p[k]) for k in p}
+    blob = _blob(torch)
+    akmc.mlp_set_params(blob, S, akmc.pack_params(p32), p["mu"], p["sigma"])
+    d_env, d_ea = torch.as_tensor(env, device="cuda"), torch.as_tensor(ea, device="cuda")
+    work = torch.empty(akmc.mlp_train_workspace_bytes(S, n), dtype=torch.uint8, device="cuda")
+    g = torch.empty(akmc.mlp_param_count(S), dtype=torch.float32, device="cuda")
+    akmc.mlp_grad(blob, S, d_env, d_ea, n, g, work)
+    lr, wd = 1e-3, 0.01
+    cfg = akmc.TrainCfg(batch=n, epochs=1, lr=lr, lr_final=lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                        weight_decay=wd, shuffle=0, seed=0)
+    akmc.mlp_train(blob, S, d_env, d_ea, n, cfg, work)
+    torch.cuda.synchronize()
+    got = akmc.unpack_params(akmc.mlp_get_params(blob, S)[0], S)
+    gd = akmc.unpack_params(g.cpu().numpy(), S)
+    ref = {k: np.array(p32[k], copy=True) for k in M.PARAM_KEYS}
+    M.adamw_step(ref, gd, {}, lr, weight_decay=wd)
+    for k in M.PARAM_KEYS:
+        assert np.max(np.abs(got[k] - ref[k])) <= 1e-6 * lr + 1e-6 * np.max(np.abs(ref[k])), k
+
+
+def test_training_learns_the_pair_barrier(oracle_mod):
+    """A few epochs on GPU-encoded data lower the held-out barrier error well
+    below the spread of the targets; OOD bounds come from the data."""
+    import torch
+    from oracle import mlp as M
+    banner("mlp training")
+    spec = W.rpv_524k()
+    lat = akmc.Lattice(spec)
+    rng = np.random.default_rng(8)
+    sites = rng.choice(spec.n_sites, 40000, replace=False).astype(np.int32)
+    d_sites = torch.as_tensor(sites, device="cuda")
+    env = torch.empty((len(sites) * 8, 27), dtype=torch.uint8, device="cuda")
+    ea = torch.empty(len(sites) * 8, dtype=torch.float32, device="cuda")
+    akmc.env_encode(lat.h, akmc.RATES_SITES, d_sites, len(sites), env, ea)
+    torch.cuda.synchronize()
+    lat.close()
+    n_train = 280000
+    mu, sigma = float(ea[:n_train][torch.isfinite(ea[:n_train])].mean()), float(ea[:n_train][torch.isfinite(ea[:n_train])].std())
+    blob = _blob(torch)
+    akmc.mlp_init(blob, S, 11, mu, sigma)
+    akmc.mlp_fit_ood(blob, S, env, n_train)
+    cfg = akmc.TrainCfg(batch=256, epochs=4, lr=2e-3, lr_final=2e-5, beta1=0.9, beta2=0.999, eps=1e-8,
+                        weight_decay=0.0, shuffle=1, seed=5)
+    work = torch.empty(akmc.mlp_train_workspace_bytes(S, 256), dtype=torch.uint8, device="cuda")
+    steps = 4 * ((n_train + 255) // 256)
+    loss = torch.empty(steps, dtype=torch.float32, device="cuda")
+    akmc.mlp_train(blob, S, env, ea, n_train, cfg, work, loss)
+    pred = torch.empty(len(ea) - n_train, dtype=torch.float32, device="cuda")
+    akmc.mlp_forward(blob, S, env[n_train:], len(ea) - n_train, pred)
+    torch.cuda.synchronize()
+    l = loss.cpu().numpy()
+    assert np.all(np.isfinite(l)) and l[-200:].mean() < 0.05 * l[:50].mean()
+    t = ea[n_train:].cpu().numpy().astype(np.float64)
+    m = np.isfinite(t)
+    err = pred.cpu().numpy()[m].astype(np.float64) - t[m]
+    rmse_mev = 1000 * np.sqrt(np.mean(err ** 2))
+    print("held-out rmse %.2f meV (target spread %.1f meV)" % (rmse_mev, 1000 * t[m].std()))
+    assert rmse_mev < 15.0
+    # The trained weights reproduce on the oracle (bf16 roundings).
+    params, mu2, sg2 = akmc.mlp_get_params(blob, S)
+    pd = akmc.unpack_params(params, S)
+    pd["mu"], pd["sigma"] = mu2, sg2
+    e_host = env[n_train:n_train + 2000].cpu().numpy()
+    ref = M.predict_ea(pd, e_host, S, bf16_act=True)
+    assert np.max(np.abs(ref - pred[:2000].cpu().numpy())) <= 2e-3
+
+
+def test_mlp_loop_constant_network_equals_pair_model():
+    """Learned barrier inside the event loop, exactly checkable: a network
+    whose output is the constant E0(Fe), with out-of-distribution bounds
+    fitted on the all-Fe environment.  Every all-Fe candidate then gets the
+    pair barrier's value from the network, every other candidate falls back
+    to the pair barrier, so the trajectory must equal the binary32 pair
+    trajectory bit for bit, and the fallbacks are counted."""
+    import torch
+    banner("mlp loop constant network")
+    spec = W.random_lattice(np.random.default_rng(12), (14, 14, 14), S, 25, solute_total=0.03)
+    n = 20000
+    ref = akmc.Lattice(spec, precision=akmc.FP32)
+    buf_r = ref.step(n, log=True)
+    blob = _blob(torch)
+    zero = np.zeros(akmc.mlp_param_count(S), dtype=np.float32)
+    akmc.mlp_set_params(blob, S, zero, float(np.float32(spec.e0[0])), 1.0)
+    fe_env = torch.zeros((1, 27), dtype=torch.uint8, device="cuda")
+    akmc.mlp_fit_ood(blob, S, fe_env, 1)
+    lat = akmc.Lattice(spec, precision=akmc.FP32, barrier_model=akmc.BARRIER_MLP)
+    akmc.mlp_attach(lat.h, blob)
+    buf_m = lat.step(n, log=True)
+    torch.cuda.synchronize()
+    log_r, log_m = akmc.log_to_numpy(buf_r, n), akmc.log_to_numpy(buf_m, n)
+    occ_r, _, s_r = ref.read()
+    occ_m, _, s_m = lat.read()
+    ref.close()
+    lat.close()
+    assert np.array_equal(log_r, log_m)
+    assert s_r.digest == s_m.digest and np.array_equal(occ_r, occ_m) and s_r.t == s_m.t
+    assert s_m.n_ood > 0 and s_r.n_ood == 0
+
+
+def test_mlp_loop_trained_network_runs_physically(oracle_mod):
+    """A trained surrogate drives the loop: species are conserved, the run
+    completes, fallbacks are counted, and the network's barriers for the
+    final state's candidates stay near the pair model.  The trajectory
+    carries vacancies into solute-bound environments that random-site
+    training data covers thinly, so this bound is looser than the held-out
+    error of the training test."""
+    import torch
+    banner("mlp loop trained")
+    spec = W.random_lattice(np.random.default_rng(13), (20, 20, 20), S, 30, solute_total=0.034)
+    lat0 = akmc.Lattice(spec)
+    sites = torch.arange(spec.n_sites, dtype=torch.int32, device="cuda")
+    env = torch.empty((spec.n_sites * 8, 27), dtype=torch.uint8, device="cuda")
+    ea = torch.empty(spec.n_sites * 8, dtype=torch.float32, device="cuda")
+    akmc.env_encode(lat0.h, akmc.RATES_SITES, sites, spec.n_sites, env, ea)
+    torch.cuda.synchronize()
+    lat0.close()
+    fin = torch.isfinite(ea)
+    mu, sigma = float(ea[fin].mean()), float(ea[fin].std())
+    blob = _blob(torch)
+    akmc.mlp_init(blob, S, 3, mu, sigma)
+    akmc.mlp_fit_ood(blob, S, env, len(ea))
+    cfg = akmc.TrainCfg(batch=256, epochs=3, lr=2e-3, lr_final=2e-5, beta1=0.9, beta2=0.999, eps=1e-8,
+                        weight_decay=0.0, shuffle=1, seed=1)
+    work = torch.empty(akmc.mlp_train_workspace_bytes(S, 256), dtype=torch.uint8, device="cuda")
+    akmc.mlp_train(blob, S, env, ea, len(ea), cfg, work)
+    lat = akmc.Lattice(spec, precision=akmc.FP32, barrier_model=akmc.BARRIER_MLP)
+    akmc.mlp_attach(lat.h, blob)
+    lat.step(20000)
+    occ, slots, s = lat.read()
+    # Barriers of the final state's candidates: network vs pair model.
+    env_v = torch.empty((len(slots) * 8, 27), dtype=torch.uint8, device="cuda")
+    ea_v = torch.empty(len(slots) * 8, dtype=torch.float32, device="cuda")
+    akmc.env_encode(lat.h, akmc.RATES_VACANCIES, None, 0, env_v, ea_v)
+    pred = torch.empty_like(ea_v)
+    akmc.mlp_forward(blob, S, env_v, len(ea_v), pred)
+    torch.cuda.synchronize()
+    lat.close()
+    assert np.array_equal(np.bincount(occ, minlength=S), np.bincount(spec.occ, minlength=S))
+    assert s.n_events == 20000 and s.frozen == 0
+    m = torch.isfinite(ea_v)
+    rmse = 1000 * float(torch.sqrt(torch.mean((pred[m] - ea_v[m]) ** 2)))
+    print("in-loop state barrier rmse %.2f meV, n_ood %d" % (rmse, s.n_ood))
+    assert rmse < 40.0

@@ -13,7 +13,8 @@ from tests.gpu_util import banner
 pytestmark = pytest.mark.gpu
 
 CASES = [((3, 3, 3), 3, 4, 1), ((5, 4, 6), 5, 12, 2), ((12, 12, 12), 5, 40, 3),
-         ((37, 5, 9), 5, 30, 4), ((33, 34, 35), 4, 100, 5)]
+         ((37, 5, 9), 5, 30, 4), ((33, 34, 35), 4, 100, 5), ((20, 7, 11), 8, 50, 6),
+         ((40, 9, 6), 2, 20, 7)]
 
 
 def _compare(spec, oracle_mod, precision, mode):
