@@ -65,6 +65,53 @@ def measured_traffic(bytes_per_launch_alg, precision_tag):
     return r.get("hbm_bytes_per_launch")
 
 
+def _counter_rows(run_dir, counter):
+    """(kernel name, dispatch id, value) of `counter` from a rocprofv3 CSV run."""
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                low = {k.lower(): v for k, v in r.items()}
+                if low.get("counter_name") != counter:
+                    continue
+                rows.append((low["kernel_name"], low.get("dispatch_id", ""), float(low["counter_value"])))
+    return rows
+
+
+def write_traffic(fetch_dir, write_dir, tag):
+    """HBM bytes per sweep launch from two rocprofv3 --pmc runs of
+    `bench.py --copy-calibration` (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch).  Each counter is scaled by the factor that makes it read
+    256 MiB on the calibration pass (an elementwise add over 256 MiB of
+    binary32: 256 MiB read, 256 MiB written)."""
+    calib = 256 << 20
+    out = {"source_hash": kernel_source_hash()}
+    try:
+        with open(PROFILE_TRAFFIC) as f:
+            out.update({k: v for k, v in json.load(f).items() if k in ("fp32", "fp64")})
+    except (OSError, ValueError):
+        pass
+    rec = {}
+    for name, run_dir in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(run_dir, name)
+        ew = [v for k, _, v in rows if "elementwise" in k]
+        sweep = [v for k, _, v in rows if "k_rates_all" in k]
+        if not ew or not sweep:
+            raise SystemExit("no calibration or sweep dispatch with %s under %s" % (name, run_dir))
+        factor = calib / (max(ew) * 1024.0)
+        rec[name] = {"kib_per_dispatch_mean": float(np.mean(sweep)), "dispatches": len(sweep),
+                     "calibration_kib": max(ew), "factor": factor,
+                     "bytes_per_launch": float(np.mean(sweep)) * 1024.0 * factor}
+    rec["hbm_bytes_per_launch"] = rec["FETCH_SIZE"]["bytes_per_launch"] + rec["WRITE_SIZE"]["bytes_per_launch"]
+    out[tag] = rec
+    out["source_hash"] = kernel_source_hash()
+    with open(PROFILE_TRAFFIC, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(spec, n_events):
     from oracle import akmc_oracle as O
     o = O.Oracle(spec, precision=0)
@@ -130,7 +177,94 @@ def bench_forms(args, torch, akmc, W, stream):
                                      "hipgraph": 1}}
     akmc.batch_destroy(b)
     del ws
+    if args.surrogate_samples > 0:
+        forms["surrogate"] = bench_surrogate(args, torch, akmc, W, stream)
     return forms
+
+
+MLP_FWD_FLOP = 2 * (160 * 128 + 128 * 128 + 128)     # per candidate, five species
+
+
+def bench_surrogate(args, torch, akmc, W, stream):
+    """Learned-barrier form on the same 4.2M-site lattice: training samples
+    are the 8 candidates of random sites of the binary32 pair path (labels
+    = pair barriers), the network is trained on the GPU, timed in bulk
+    inference, and then drives the event loop (out-of-distribution
+    candidates fall back to the pair barrier)."""
+    S = 5
+    spec = W.rpv_4m()
+    rng = np.random.default_rng(2024)
+    n_sites = args.surrogate_samples // 8
+    with torch.cuda.stream(stream):
+        lat = akmc.Lattice(spec, precision=akmc.FP32, stream=stream)
+        lat.step(args.events)
+        sites = torch.as_tensor(rng.choice(spec.n_sites, n_sites, replace=False).astype(np.int32),
+                                device="cuda")
+        env = torch.empty((n_sites * 8, 27), dtype=torch.uint8, device="cuda")
+        ea = torch.empty(n_sites * 8, dtype=torch.float32, device="cuda")
+        akmc.env_encode(lat.h, akmc.RATES_SITES, sites, n_sites, env, ea)
+        lat.close()
+        n = n_sites * 8
+        n_train = (n * 9 // 10) // 256 * 256
+        fin = torch.isfinite(ea[:n_train])
+        mu, sigma = float(ea[:n_train][fin].mean()), float(ea[:n_train][fin].std())
+        blob = torch.zeros(akmc.mlp_blob_bytes(S), dtype=torch.uint8, device="cuda")
+        akmc.mlp_init(blob, S, 7, mu, sigma)
+        akmc.mlp_fit_ood(blob, S, env, n_train)
+        cfg = akmc.TrainCfg(batch=256, epochs=args.surrogate_epochs, lr=2e-3, lr_final=2e-5,
+                            beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, shuffle=1, seed=5)
+        work = torch.empty(akmc.mlp_train_workspace_bytes(S, 256), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        akmc.mlp_train(blob, S, env, ea, n_train, cfg, work)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        train_s = e0.elapsed_time(e1) * 1e-3
+        pred = torch.empty(n, dtype=torch.float32, device="cuda")
+        akmc.mlp_forward(blob, S, env, n, pred)
+        torch.cuda.synchronize()
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(5):
+            akmc.mlp_forward(blob, S, env, n, pred)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        fwd_s = f0.elapsed_time(f1) * 1e-3 / 5
+        t = ea[n_train:].double()
+        m = torch.isfinite(t)
+        err = pred[n_train:].double()[m] - t[m]
+        rmse_mev = 1000 * float(torch.sqrt(torch.mean(err * err)))
+
+        pair = akmc.Lattice(spec, precision=akmc.FP32, stream=stream)
+        mlp = akmc.Lattice(spec, precision=akmc.FP32, stream=stream, barrier_model=akmc.BARRIER_MLP)
+        akmc.mlp_attach(mlp.h, blob)
+        times = {}
+        for name, l in (("pair", pair), ("mlp", mlp)):
+            l.step(1000)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            l.step(args.surrogate_events)
+            b.record(stream)
+            torch.cuda.synchronize()
+            times[name] = a.elapsed_time(b) * 1e-3
+        _, _, s_m = mlp.read()
+        pair.close()
+        mlp.close()
+    fwd_flops = MLP_FWD_FLOP * n / fwd_s
+    return {"samples": n, "train_samples": n_train, "epochs": args.surrogate_epochs,
+            "train_s": train_s,
+            "train_samples_per_s": n_train * args.surrogate_epochs / train_s,
+            "train_tflops_dense_equiv": 3 * MLP_FWD_FLOP * n_train * args.surrogate_epochs / train_s / 1e12,
+            "heldout_rmse_mev": rmse_mev,
+            "forward_rows_per_s": n / fwd_s,
+            "forward_tflops_dense_equiv": fwd_flops / 1e12,
+            "forward_frac_of_bf16_peak": fwd_flops / 2.5e15,
+            "loop_events_per_s": args.surrogate_events / times["mlp"],
+            "pair_loop_events_per_s": args.surrogate_events / times["pair"],
+            "loop_speedup_vs_pair": times["pair"] / times["mlp"],
+            "ood_fallbacks_per_event": s_m.n_ood / (args.surrogate_events + 1000)}
 
 
 def main():
@@ -140,13 +274,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--events", type=int, default=100_000, help="events per step")
     ap.add_argument("--batch-events", type=int, default=2_000, help="events per replica (batched form)")
-    ap.add_argument("--cpu-events", type=int, default=10_000, help="oracle sample size")
+    ap.add_argument("--cpu-events", type=int, default=30_000, help="oracle sample size (about 15 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--fp64", action="store_true", help="time the binary64 path as the main line")
+    ap.add_argument("--surrogate-samples", type=int, default=2_000_000,
+                    help="training+held-out candidates of the learned-barrier form (0 = skip it)")
+    ap.add_argument("--surrogate-epochs", type=int, default=1)
+    ap.add_argument("--surrogate-events", type=int, default=20_000)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one 256 MiB device-to-device copy (reference for HBM counters)")
+                    help="also run one elementwise pass over 256 MiB (reads 256 MiB, writes "
+                         "256 MiB): the reference for the HBM byte counters")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this "
+                         "script with --copy-calibration into the committed traffic record, then exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(args.traffic_from[0], args.traffic_from[1], "fp64" if args.fp64 else "fp32")
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path of one lattice runs on one device, and "
               "replica ensembles shard across GPUs without communication (not run here); "
@@ -240,11 +385,11 @@ def main():
                        "bound": "per-event dependency chain on one CU (latency)"},
     }
     if args.copy_calibration:
-        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        line["copy_calibration_bytes"] = src.numel()
+        line["copy_calibration_bytes"] = src.numel() * 4
         del src, dst
     if not args.no_forms:
         line["forms"] = bench_forms(args, torch, akmc, W, stream)

@@ -156,8 +156,10 @@ akmc_status akmc_lattice_create(const akmc_params *p, const uint8_t *occ_host,
  * AKMC_FP64 and float for AKMC_FP32.  d_ea_out (same type and shape, may
  * be NULL) receives the barriers.  d_sites: device int32 site list for
  * AKMC_RATES_SITES (ignored otherwise); a listed site outside [0, N) gets
- * NaN rates and barriers.  Asynchronous.  Errors: INVALID (mode, NULL
- * output or site list). */
+ * NaN rates and barriers.  AKMC_RATES_ALL_SITES writes 16-byte vectors:
+ * its outputs must be 16-byte aligned (hipMalloc and torch allocations
+ * are).  Asynchronous.  Errors: INVALID (mode, NULL output or site list,
+ * misaligned ALL_SITES output). */
 akmc_status akmc_rates_eval(akmc_handle h, int32_t mode, const int32_t *d_sites,
                             int64_t n_sites, void *d_rates_out, void *d_ea_out);
 
@@ -174,6 +176,22 @@ akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log);
  * NULL. */
 akmc_status akmc_state_read(akmc_handle h, uint8_t *occ_host, int32_t *slot_sites_host,
                             akmc_summary *out);
+
+/* Cluster-size histogram of one species: connected components under
+ * first-neighbour adjacency on the periodic lattice (clustering descriptor
+ * of Sec. III-A2; Cu-rich precipitates of Sec. III-C1).  Off the event
+ * path: it reads the lattice as the last enqueued step leaves it.
+ *   species   code in [0, n_species)
+ *   max_size  >= 1; d_hist (device int64[max_size + 1]) receives in
+ *             hist[s] the number of clusters of size s for 1 <= s <
+ *             max_size and in hist[max_size] those of size >= max_size;
+ *             hist[0] = 0
+ *   d_scratch device memory of at least akmc_cluster_scratch_bytes bytes,
+ *             borrowed for the call (two int32 per site)
+ * Errors: INVALID, WORKSPACE.  Asynchronous on the handle's stream. */
+akmc_status akmc_cluster_scratch_bytes(akmc_handle h, size_t *bytes);
+akmc_status akmc_cluster_hist(akmc_handle h, int32_t species, int64_t max_size,
+                              int64_t *d_hist, void *d_scratch, size_t scratch_bytes);
 
 /* Releases the host-side handle.  Does not free d_ws. */
 akmc_status akmc_lattice_destroy(akmc_handle h);

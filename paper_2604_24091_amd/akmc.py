@@ -94,6 +94,8 @@ def lib():
         L.akmc_kmc_step.argtypes = [vp, C.c_int64, vp]
         L.akmc_state_read.argtypes = [vp, vp, vp, C.POINTER(Summary)]
         L.akmc_lattice_destroy.argtypes = [vp]
+        L.akmc_cluster_scratch_bytes.argtypes = [vp, C.POINTER(sz)]
+        L.akmc_cluster_hist.argtypes = [vp, C.c_int32, C.c_int64, vp, vp, sz]
         L.akmc_batch_workspace_bytes.argtypes = [C.c_int32, P, vp, C.POINTER(sz)]
         L.akmc_batch_create.argtypes = [C.c_int32, P, vp, vp, vp, sz, vp, C.POINTER(vp)]
         L.akmc_batch_set_schedule.argtypes = [vp, C.POINTER(Schedule)]
@@ -234,6 +236,17 @@ def state_read(h: int, occ_host: Optional[np.ndarray] = None,
 
 def lattice_destroy(h: int):
     _check(lib().akmc_lattice_destroy(h), "lattice_destroy")
+
+
+def cluster_scratch_bytes(h: int) -> int:
+    out = C.c_size_t(0)
+    _check(lib().akmc_cluster_scratch_bytes(h, C.byref(out)), "cluster_scratch_bytes")
+    return out.value
+
+
+def cluster_hist(h: int, species: int, max_size: int, hist_out, scratch, scratch_bytes: int):
+    _check(lib().akmc_cluster_hist(h, int(species), int(max_size), _ptr(hist_out), _ptr(scratch),
+                                   int(scratch_bytes)), "cluster_hist")
 
 
 def batch_workspace_bytes(params: Sequence[Params], n_vac: Sequence[int]) -> int:
@@ -423,6 +436,18 @@ class Lattice:
             buf = torch.empty((max(n_events, 1), 40), dtype=torch.uint8, device=self.ws.device)
         kmc_step(self.h, n_events, buf)
         return buf
+
+    def clusters(self, species: int = 1, max_size: int = 64):
+        """Device int64[max_size + 1] cluster-size histogram of `species`."""
+        import torch
+        dev = self.ws.device
+        nb = cluster_scratch_bytes(self.h)
+        # Kept with the lattice: the launch is asynchronous on its stream.
+        if getattr(self, "_cc_scratch", None) is None:
+            self._cc_scratch = torch.empty(nb, dtype=torch.uint8, device=dev)
+        hist = torch.empty(max_size + 1, dtype=torch.int64, device=dev)
+        cluster_hist(self.h, species, max_size, hist, self._cc_scratch, nb)
+        return hist
 
     def read(self):
         occ = np.empty(self.n_sites, dtype=np.uint8)

@@ -279,6 +279,9 @@ akmc_status akmc_rates_eval(akmc_handle h, int32_t mode, const int32_t *d_sites,
                              d_rates_out, d_ea_out, h->stream);
       break;
     case AKMC_RATES_ALL_SITES:
+      if ((reinterpret_cast<uintptr_t>(d_rates_out) & 15) ||
+          (reinterpret_cast<uintptr_t>(d_ea_out) & 15))
+        return fail(AKMC_ERR_INVALID, "ALL_SITES outputs must be 16-byte aligned");
       e = launch_rates_all(h->d_desc, h->h_desc, h->d_occ, h->p.precision, d_rates_out, d_ea_out,
                            h->stream);
       break;
@@ -372,6 +375,32 @@ akmc_status akmc_state_read(akmc_handle h, uint8_t *occ_host, int32_t *slot_site
   if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
   return read_state(h->stream, h->d_desc, h->h_desc, h->d_state, h->d_occ, h->d_slots,
                     h->d_scratch, h->nv, h->nsites, h->p.precision, occ_host, slot_sites_host, out);
+}
+
+akmc_status akmc_cluster_scratch_bytes(akmc_handle h, size_t *bytes) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (!bytes) return fail(AKMC_ERR_INVALID, "bytes is NULL");
+  *bytes = 2 * up(sizeof(int32_t) * (size_t)h->nsites);
+  return AKMC_OK;
+}
+
+akmc_status akmc_cluster_hist(akmc_handle h, int32_t species, int64_t max_size, int64_t *d_hist,
+                              void *d_scratch, size_t scratch_bytes) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (species < 0 || species >= h->p.n_species)
+    return fail(AKMC_ERR_INVALID, "species must lie in [0, n_species)");
+  if (max_size < 1 || max_size > h->nsites)
+    return fail(AKMC_ERR_INVALID, "max_size must lie in [1, number of sites]");
+  if (!d_hist) return fail(AKMC_ERR_INVALID, "histogram output is NULL");
+  const size_t half = up(sizeof(int32_t) * (size_t)h->nsites);
+  if (!d_scratch) return fail(AKMC_ERR_INVALID, "scratch is NULL");
+  if (scratch_bytes < 2 * half) return fail(AKMC_ERR_WORKSPACE, "cluster scratch too small");
+  int32_t *parent = static_cast<int32_t *>(d_scratch);
+  int32_t *size = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(d_scratch) + half);
+  const hipError_t e = launch_cluster_hist(h->d_occ, h->p.lx, h->p.ly, h->p.lz, species, max_size,
+                                           d_hist, parent, size, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "cluster_hist launch");
+  return AKMC_OK;
 }
 
 akmc_status akmc_lattice_destroy(akmc_handle h) {

@@ -134,6 +134,9 @@ hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_spec
                                  hipStream_t stream);
 size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision);
 hipError_t launch_queue_reset(int32_t *queue, hipStream_t stream);
+hipError_t launch_cluster_hist(const uint8_t *d_occ, int lx, int ly, int lz, int species,
+                               int64_t max_size, int64_t *d_hist, int *d_parent, int *d_size,
+                               hipStream_t st);
 
 hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h_desc, const uint8_t *occ,
                               const int32_t *sites, int64_t n_sites, int precision,

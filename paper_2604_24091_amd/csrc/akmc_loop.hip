@@ -176,7 +176,6 @@ __host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
 template <int G, class Real, bool MLP = false>
 struct Runner {
   LoopArgs a;
-  int qo1, qo2, qo3, qo4;   // level offsets in the tree region
   Group<G> gp;
   int foot[8];
   Lds<Real> s;
@@ -191,6 +190,7 @@ struct Runner {
   float mu, sigma;
   int k1;
   int64_t n_ood;
+  double top_q;   // lane c < 8: partial c of the top tree level (cached between events)
 
   __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
                     const int (&foot_)[8], unsigned char *lds)
@@ -220,17 +220,19 @@ struct Runner {
       if (gp.gl < 40) ml.ood[gp.gl] = hdr->ood_valid ? hdr->ood_max[gp.gl >> 3][gp.gl & 7] : 64;
       gsync();
     }
-    qo1 = L.qoff[1];
-    qo2 = L.qoff[2];
-    qo3 = L.qoff[3];
-    qo4 = L.qoff[4];
 #pragma unroll
     for (int m = 0; m < 8; ++m) foot[m] = foot_[m];
   }
 
-  // Level l (1-based) of the tree: its nodes and their count.
+  // Level l (1-based) of the tree: its nodes and their count.  Level m of
+  // the layout holds ceil(nv_max / 8^(m-1)) nodes.
   __device__ __forceinline__ double *Q(int l) const {
-    return s.q + (l == 1 ? qo1 : l == 2 ? qo2 : l == 3 ? qo3 : qo4);
+    int o = 0;
+    for (int m = 1; m < l; ++m) {
+      const int sh = 3 * (m - 1);
+      o += (a.nv_max + (1 << sh) - 1) >> sh;
+    }
+    return s.q + o;
   }
   __device__ __forceinline__ int nl(int l) const {
     const int sh = 3 * (l - 1);
@@ -243,18 +245,71 @@ struct Runner {
     return Q(l - 1)[8 * u + cnt - 1];
   }
 
-  // Inclusive left-to-right sums within each 8-lane subgroup: lane c of
-  // subgroup q returns x_0 + x_1 + ... + x_c of that subgroup's values.
-  __device__ __forceinline__ double subgroup_prefix(double x, int q, int c) {
-    s.tmp[gp.gl] = x;
-    gsync();
-    const double *t = s.tmp + (q << 3);
-    double acc = t[0];
+  // Value held by lane c-D of the same 16-lane row (DPP row_shr:D).
+  template <int D>
+  __device__ __forceinline__ static double row_shr(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), 0x110 + D, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), 0x110 + D, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+  }
+
+  // Inclusive sums within each 8-lane subgroup in a fixed order
+  // (Kogge-Stone: y <- y[c-d] + y[c] for d = 1, 2, 4, where c >= d): lane c
+  // returns the sum of x_0..x_c.  The order depends only on the 8 values,
+  // never on how many lanes serve a lattice.  Every lane of the wavefront
+  // must execute it.
+  __device__ __forceinline__ static double subgroup_prefix(double x, int c) {
+    double y = x;
+    double t = row_shr<1>(y);
+    if (c >= 1) y = t + y;
+    t = row_shr<2>(y);
+    if (c >= 2) y = t + y;
+    t = row_shr<4>(y);
+    if (c >= 4) y = t + y;
+    return y;
+  }
+
+  // Value of x in lane src of this group (src uniform over the group).
+  __device__ __forceinline__ double lane_value(double x, int src) const {
+    if (G == 64) {
+      const int lo = __builtin_amdgcn_readlane(__double2loint(x), src);
+      const int hi = __builtin_amdgcn_readlane(__double2hiint(x), src);
+      return __hiloint2double(hi, lo);
+    }
+    return __shfl(x, gp.base + src, 64);
+  }
+
+  // Re-sums the tree path above one refreshed slot v: every level's node
+  // values are read up front, the one node on the path takes the value just
+  // computed below it, and each level's partials come from subgroup_prefix.
+  // Returns Gamma_tot.
+  __device__ double update_path(int v) {
+    const int c = gp.gl & 7;
+    const bool worker = gp.gl < 8;
+    double x[kMaxLevels + 1];
 #pragma unroll
-    for (int m = 1; m < 8; ++m)
-      if (m <= c) acc = acc + t[m];
+    for (int l = 1; l <= kMaxLevels; ++l) {
+      x[l] = 0.0;
+      if (l <= nlev) {
+        const int u = 8 * (v >> (3 * l)) + c;
+        if (worker && u < nl(l)) x[l] = node_value(l, u);
+      }
+    }
+    double fresh = 0.0;
+#pragma unroll
+    for (int l = 1; l <= kMaxLevels; ++l) {
+      if (l <= nlev) {
+        const int g = v >> (3 * l);
+        if (l > 1 && c == ((v >> (3 * (l - 1))) & 7)) x[l] = fresh;
+        const double pfx = subgroup_prefix(x[l], c);
+        const int cnt = min(8, nl(l) - 8 * g);
+        if (worker && c < cnt) Q(l)[8 * g + c] = pfx;
+        if (l == nlev) top_q = pfx;
+        fresh = lane_value(pfx, cnt - 1);
+      }
+    }
     gsync();
-    return acc;
+    return fresh;
   }
 
   // Learned-barrier rates of one refresh pass (all 64 lanes take part in the
@@ -379,7 +434,7 @@ struct Runner {
         r = eval_mlp_pass(np, q, k, p0, vv);
       }
       // part[v][k] = r0 + r1 + ... + rk
-      const double acc = subgroup_prefix(r, q, k);
+      const double acc = subgroup_prefix(r, k);
       if (q < np) s.part[vv * 8 + k] = acc;
       gsync();
     }
@@ -417,7 +472,7 @@ struct Runner {
         cnt = min(8, nl(l) - base);
         if (c < cnt) x = node_value(l, base + c);
       }
-      const double acc = subgroup_prefix(x, q, c);
+      const double acc = subgroup_prefix(x, c);
       if (live && c < cnt) Q(l)[base + c] = acc;
       gsync();
     }
@@ -434,7 +489,10 @@ struct Runner {
     }
   }
 
-  __device__ double gamma_tot() const { return Q(nlev)[nl(nlev) - 1]; }
+  __device__ double gamma_tot() {
+    top_q = gp.gl < nl(nlev) ? Q(nlev)[gp.gl] : 0.0;
+    return Q(nlev)[nl(nlev) - 1];
+  }
 
   __device__ void run(int lat) {
     const LatDesc *d = a.descs + lat;
@@ -493,39 +551,72 @@ struct Runner {
       const double u1 = s.ru1[ce], w = s.rw[ce];
       double tgt = u1 * gtot;
 
-      // Selection: descend the tree of partial sums.
+      // Selection: descend the tree of partial sums.  Levels nlev..1 hold
+      // the slot tree; level 0 is the per-direction partials part[8v + k].
+      // At each level the child is the first whose inclusive partial sum
+      // exceeds the target, and the target drops by the partial sum before
+      // it.  A full wavefront takes two levels per LDS round trip (lane
+      // 8c + c' looks at grandchild c' of child c); the comparisons and
+      // subtractions are the same, so the result does not depend on G.
       int node = 0;
-      for (int l = nlev; l >= 1; --l) {
+      int l = nlev;
+      while (l >= 0) {
         const int base = (l == nlev) ? 0 : node * 8;
-        const int cnt = min(8, nl(l) - base);
-        const double *qq = Q(l) + base;
+        if (G == 64 && l >= 1) {
+          const int c = gl >> 3, c2 = gl & 7;
+          const int cntA = min(8, nl(l) - base);
+          const bool inA = c < cntA;
+          const double *qa_p = Q(l) + base;
+          const double qa = inA ? qa_p[c] : 0.0;
+          const double qp = (inA && c > 0) ? qa_p[c - 1] : 0.0;
+          const int baseB = 8 * (base + c);
+          const int nlB = l >= 2 ? nl(l - 1) : 8 * nv;
+          const bool inB = inA && c2 < min(8, nlB - baseB);
+          const double qb = inB ? (l >= 2 ? Q(l - 1)[baseB + c2] : s.part[baseB + c2]) : 0.0;
+          const uint64_t mA = gp.ballot(c2 == 0 && inA && qa > tgt);
+          if (mA) {
+            const int cs = (__ffsll((unsigned long long)mA) - 1) >> 3;
+            const double t1 = c > 0 ? tgt - qp : tgt;
+            const uint64_t mB = gp.ballot(c == cs && inB && qb > t1);
+            const double t1u = lane_value(t1, 8 * cs);
+            if (mB) {
+              const int cb = (__ffsll((unsigned long long)mB) - 1) & 7;
+              const double qbp = lane_value(qb, 8 * cs + (cb > 0 ? cb - 1 : 0));
+              tgt = cb > 0 ? t1u - qbp : t1u;
+              node = 8 * (base + cs) + cb;
+              l -= 2;
+            } else {
+              // No grandchild exceeds the target (rounding): the single
+              // step below takes level l-1's fallback.
+              tgt = t1u;
+              node = base + cs;
+              l -= 1;
+            }
+            continue;
+          }
+        }
+        const int cnt = l >= 1 ? min(8, nl(l) - base) : 8;
         const bool in = gl < cnt;
-        const double qv = in ? qq[gl] : 0.0;
+        double qv = 0.0;
+        if (in) qv = l == 0 ? s.part[base + gl] : (l == nlev ? top_q : Q(l)[base + gl]);
         uint64_t m = gp.ballot(in && (qv > tgt)) & 0xffull;
         int c;
         if (m) {
           c = __ffsll((unsigned long long)m) - 1;
-        } else {
+        } else if (l >= 1) {
           const double cv = in ? node_value(l, base + gl) : 0.0;
           const uint64_t m2 = gp.ballot(in && (cv > 0.0)) & 0xffull;
           c = m2 ? 63 - __clzll((long long)m2) : 0;
-        }
-        if (c > 0) tgt = tgt - qq[c - 1];
-        node = base + c;
-      }
-      const int v = node;
-      int k;
-      {
-        const bool in = gl < 8;
-        const double pv = in ? s.part[v * 8 + gl] : 0.0;
-        uint64_t m = gp.ballot(in && (pv > tgt)) & 0xffull;
-        if (m) {
-          k = __ffsll((unsigned long long)m) - 1;
         } else {
-          const uint64_t m2 = gp.ballot(in && (s.spec[v * 8 + gl] != V)) & 0xffull;
-          k = m2 ? 63 - __clzll((long long)m2) : 0;
+          const uint64_t m2 = gp.ballot(in && (s.spec[base + gl] != V)) & 0xffull;
+          c = m2 ? 63 - __clzll((long long)m2) : 0;
         }
+        const double prev = lane_value(qv, c > 0 ? c - 1 : 0);
+        if (c > 0) tgt = tgt - prev;
+        node = base + c;
+        l -= 1;
       }
+      const int v = node >> 3, k = node & 7;
       const int A = s.spec[v * 8 + k];
       const int pp = s.pos[v];
       const int X = pos_x(pp), Y = pos_y(pp), Z = pos_z(pp);
@@ -545,41 +636,98 @@ struct Runner {
       rec.gamma_tot = gtot;
       rec.dt = dt;
       akmc_event *ev = evlog ? evlog + e : nullptr;
+
+      // Stores of earlier events are complete before any gather.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      // Footprint of the moved vacancy around its new site j, gathered
+      // before the swap is stored; the two swapped sites are patched below.
+      int site0[8];
+      uint8_t val0[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int f = foot[m];
+        site0[m] = -1;
+        val0[m] = (uint8_t)V;
+        if (f < 0 || ((f >> 18) & 63) != 0 || (f & (1 << 24))) continue;
+        const int FX = wrapc(JX + ((f >> 9) & 7) - 3, g.X2);
+        const int FY = wrapc(JY + ((f >> 12) & 7) - 3, g.Y2);
+        const int FZ = wrapc(JZ + ((f >> 15) & 7) - 3, g.Z2);
+        site0[m] = site_of(g, FX, FY, FZ);
+        val0[m] = occ[site0[m]];
+      }
+      if (gl == 0) {
+        occ[si] = (uint8_t)A;
+        occ[sj] = (uint8_t)V;
+        if (ev) *ev = rec;
+      }
       gsync();
       if (gl == 0) s.pos[v] = pack_pos(JX, JY, JZ);
       gsync();
 
-      // Slots whose footprint may contain i or j.
+      // Slots whose footprint may contain i or j (always v itself).
       int na;
       if (full) {
         na = nv;
       } else {
         na = 0;
-        for (int b0 = 0; b0 < nv; b0 += G) {
-          const int vv = b0 + gl;
-          bool hit = false;
-          if (vv < nv) {
-            const int q = s.pos[vv];
-            int dx = abs(pos_x(q) - X), dy = abs(pos_y(q) - Y), dz = abs(pos_z(q) - Z);
+        for (int b0 = 0; b0 < nv; b0 += 4 * G) {
+          int qp[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int vv = b0 + u * G + gl;
+            qp[u] = vv < nv ? s.pos[vv] : -1;
+          }
+          bool hit[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            int dx = abs(pos_x(qp[u]) - X), dy = abs(pos_y(qp[u]) - Y), dz = abs(pos_z(qp[u]) - Z);
             dx = min(dx, g.X2 - dx);
             dy = min(dy, g.Y2 - dy);
             dz = min(dz, g.Z2 - dz);
-            hit = max(dx, max(dy, dz)) <= 4;
+            hit[u] = qp[u] >= 0 && max(dx, max(dy, dz)) <= 4;
           }
-          const uint64_t m = gp.ballot(hit);
-          if (hit) s.aff[na + __popcll(m & gp.lanes_below())] = vv;
-          na += __popcll(m);
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint64_t m = gp.ballot(hit[u]);
+            if (hit[u]) s.aff[na + __popcll(m & gp.lanes_below())] = b0 + u * G + gl;
+            na += __popcll(m);
+          }
         }
         gsync();
       }
       t += dt;
       dig = fnv_event(dig, n, si, sj);
       n += 1;
-      // Occupancy stores of earlier events complete before the gathers.
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      refresh(na, si, sj, A, true, ev, rec);
-      update_tree(na);
-      gtot = gamma_tot();
+
+      if (!MLP && na == 1) {
+        // Only the moved vacancy: its box is already gathered.
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int f = foot[m];
+          if (f < 0 || ((f >> 18) & 63) != 0) continue;
+          uint8_t v8 = val0[m];
+          if (f & (1 << 24)) v8 = (uint8_t)V;
+          else if (site0[m] == si) v8 = (uint8_t)A;
+          else if (site0[m] == sj) v8 = (uint8_t)V;
+          s.box[f & 511] = v8;
+        }
+        gsync();
+        const int kk = gl & 7;
+        double r = 0.0;
+        if (gl < 8) {
+          int Ak;
+          r = eval_box<Real>(s.box, kk, S, s.D1, s.D2, s.e0, nu, kT, Ak);
+          s.spec[v * 8 + kk] = (uint8_t)Ak;
+        }
+        const double pfx = subgroup_prefix(r, kk);
+        if (gl < 8) s.part[v * 8 + kk] = pfx;
+        gsync();
+        gtot = update_path(v);
+      } else {
+        refresh(na, si, sj, A, false, nullptr, rec);
+        update_tree(na);
+        gtot = gamma_tot();
+      }
       frozen = !(gtot > 0.0);
     }
 

@@ -8,7 +8,7 @@
 //  k_rates_all: the bulk sweep over every lattice site (a vacancy placed
 //    at each site in turn).  It is bound by the HBM write of the
 //    [N][8] rate array.  A workgroup stages a brick of occupancy with a
-//    2-cell halo in LDS, computes for every site q that can be a jump
+//    halo of 2 cells (4 along x, for dword-aligned rows) in LDS, computes for every site q that can be a jump
 //    target the field H(q) = sum over its 14 bonds of
 //        D'_k[s_q][s_n] = D_k[s_q][s_n] - D_k[s_q][Fe],
 //    and for every site p of the brick the same field G'_A(p) for each
@@ -134,7 +134,11 @@ constexpr int kSweepThreads = 256;
 
 template <int TX, int TY, int TZ>
 struct SweepShape {
-  static constexpr int EX = TX + 4, EY = TY + 4, EZ = TZ + 4, EV = EX * EY * EZ;  // occupancy brick
+  // Occupancy brick: cells [-2, T+2) in y and z and [-4, T+4) in x, so that
+  // every row starts on a 4-byte boundary and can be staged in dwords.
+  static constexpr int PX = 4;
+  static constexpr int EX = TX + 2 * PX, EY = TY + 4, EZ = TZ + 4, EV = EX * EY * EZ;
+  static constexpr int ROWS = 2 * EY * EZ;
   static constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, HV = HX * HY * HZ;  // field region
   static constexpr int NT = 2 * TX * TY * TZ;                                     // brick sites
   static constexpr int OCC_BYTES = (2 * EV + 15) & ~15;
@@ -148,26 +152,31 @@ struct SweepShape {
 // h = c + b.  The targets of a corner at cell c are the centres at cells
 // c - 1 + [s > 0], those of a centre the corners at c + [s > 0]; both sit
 // at index h = c + [s > 0] of the other sublattice.
-template <int TX, int TY, int TZ, class Real, bool WITH_EA>
+//
+// Output: LPS lanes share a site, each writing 16 contiguous bytes (CPL
+// candidates), so one store instruction of a wavefront covers a
+// contiguous kilobyte of the rate array.
+template <int TX, int TY, int TZ, int S, class Real, bool WITH_EA>
 __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__restrict__ d,
                                                              const uint8_t *__restrict__ occ,
                                                              Real *__restrict__ rates,
                                                              Real *__restrict__ ea) {
   using Sh = SweepShape<TX, TY, TZ>;
-  constexpr int EX = Sh::EX, EY = Sh::EY, EV = Sh::EV;
+  constexpr int EX = Sh::EX, EY = Sh::EY, EZ = Sh::EZ, EV = Sh::EV, PX = Sh::PX;
   constexpr int HX = Sh::HX, HY = Sh::HY, HV = Sh::HV;
+  constexpr int V = S - 1, NA = S - 1;
+  constexpr int VW = 16 / (int)sizeof(Real);  // candidates per 16-byte store
+  constexpr int LPS = 8 / VW;                 // lanes per site
+  typedef Real vecw __attribute__((ext_vector_type(VW)));
   extern __shared__ __align__(16) unsigned char sweep_lds[];
   uint8_t *socc = sweep_lds;
   Real *sG = (Real *)(sweep_lds + Sh::OCC_BYTES);
-  __shared__ Real sDs1[64], sDs2[64], sC[64], sK[64], se0[8];
+  __shared__ Real sC[64], se0[8], sK[64];
 
   const int tid = threadIdx.x;
   const int lx = d->lx, ly = d->ly, lz = d->lz;
-  const int S = d->S, V = S - 1, NA = S - 1;
   const int ncell = lx * ly * lz;
   if (tid < 64) {
-    sDs1[tid] = Tab<Real>::Ds1(d)[tid];
-    sDs2[tid] = Tab<Real>::Ds2(d)[tid];
     sC[tid] = Sweep<Real>::C(d, tid);
     sK[tid] = Tab<Real>::K(d)[tid];
   }
@@ -179,37 +188,61 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
   const int y0 = ((tile / ntx) % nty) * TY;
   const int z0 = (tile / (ntx * nty)) * TZ;
 
-  // Phase 1: occupancy brick, cells [-2, T+2) of both sublattices, x fastest
-  // across lanes.  One conditional wrap suffices when every edge exceeds
-  // the brick; smaller lattices take the general modulo.
+  // Phase 1: occupancy brick of both sublattices.  One conditional wrap per
+  // axis suffices when every edge exceeds the brick (then x is staged in
+  // aligned dwords if lx is a multiple of 4); small lattices take the
+  // general modulo byte by byte.
   const bool simple = lx > TX + 2 && ly > TY + 2 && lz > TZ + 2;
-  for (int r = tid; r < 2 * EV; r += kSweepThreads) {
-    const int ex = r % EX;
-    const int row = r / EX;
-    const int ey = row % EY;
-    const int bz = row / EY;
-    const int ez = bz % Sh::EZ;
-    const int b = bz / Sh::EZ;
-    int gx = x0 + ex - 2, gy = y0 + ey - 2, gz = z0 + ez - 2;
-    if (simple) {
+  if (simple && (lx & 3) == 0) {
+    // 16 lanes per brick row (DW <= 16 dwords used), rows in pow-2 strides.
+    constexpr int DW = EX / 4;
+    static_assert(DW <= 16, "brick row wider than 16 dwords");
+    const int w = tid & 15;
+    for (int row = tid >> 4; row < Sh::ROWS; row += kSweepThreads / 16) {
+      if (w >= DW) continue;
+      const int ey = row % EY;
+      const int bz = row / EY;
+      const int ez = bz % EZ;
+      const int b = bz / EZ;
+      int gx = x0 - PX + 4 * w, gy = y0 + ey - 2, gz = z0 + ez - 2;
       gx += gx < 0 ? lx : 0;  gx -= gx >= lx ? lx : 0;
       gy += gy < 0 ? ly : 0;  gy -= gy >= ly ? ly : 0;
       gz += gz < 0 ? lz : 0;  gz -= gz >= lz ? lz : 0;
-    } else {
-      gx = ((gx % lx) + lx) % lx;
-      gy = ((gy % ly) + ly) % ly;
-      gz = ((gz % lz) + lz) % lz;
+      const uint32_t v = *(const uint32_t *)(occ + (size_t)b * ncell + (gz * ly + gy) * lx + gx);
+      *(uint32_t *)(socc + row * EX + 4 * w) = v << 2;  // codes < 8: no carry between bytes
     }
-    socc[r] = occ[b * ncell + (gz * ly + gy) * lx + gx];
+  } else {
+    for (int r = tid; r < 2 * EV; r += kSweepThreads) {
+      const int ex = r % EX;
+      const int row = r / EX;
+      const int ey = row % EY;
+      const int bz = row / EY;
+      const int ez = bz % EZ;
+      const int b = bz / EZ;
+      int gx = x0 + ex - PX, gy = y0 + ey - 2, gz = z0 + ez - 2;
+      if (simple) {
+        gx += gx < 0 ? lx : 0;  gx -= gx >= lx ? lx : 0;
+        gy += gy < 0 ? ly : 0;  gy -= gy >= ly ? ly : 0;
+        gz += gz < 0 ? lz : 0;  gz -= gz >= lz ? lz : 0;
+      } else {
+        gx = ((gx % lx) + lx) % lx;
+        gy = ((gy % ly) + ly) % ly;
+        gz = ((gz % lz) + lz) % lz;
+      }
+      socc[r] = (uint8_t)(occ[(size_t)b * ncell + (gz * ly + gy) * lx + gx] << 2);
+    }
   }
   __syncthreads();
 
   auto oidx = [&](int b, int cx, int cy, int cz) {
-    return b * EV + ((cz + 2) * EY + (cy + 2)) * EX + (cx + 2);
+    return b * EV + ((cz + 2) * EY + (cy + 2)) * EX + (cx + PX);
   };
 
   // Phase 2: G'_A(q) for every mover species A at every region site:
   //   G'_A(q) = sum_s n1_s(q) Ds1[A][s] + n2_s(q) Ds2[A][s]   (s = 0 drops out)
+  // The brick holds 4*species, the shift of that species' count nibble.
+  // The tables are uniform over the grid and stay in scalar registers.
+  const Real *Ds1 = Tab<Real>::Ds1(d), *Ds2 = Tab<Real>::Ds2(d);
   for (int r = tid; r < 2 * HV; r += kSweepThreads) {
     const int hx = r % HX;
     const int row = r / HX;
@@ -218,71 +251,88 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
     const int hz = bz % Sh::HZ;
     const int b = bz / Sh::HZ;
     const int cx = hx - b, cy = hy - b, cz = hz - b;
-    const int o = b ? 0 : -1;  // first shell of a corner: cells c-1..c; of a centre: c..c+1
+    // First shell: the other sublattice's cube of cells c-1..c (corner) or
+    // c..c+1 (centre); second shell: same sublattice, +-1 cell per axis.
+    const uint8_t *s1 = socc + oidx(1 - b, cx - 1 + b, cy - 1 + b, cz - 1 + b);
+    const uint8_t *s2 = socc + oidx(b, cx, cy, cz);
     uint32_t c1 = 0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      c1 += onehot(socc[oidx(1 - b, cx + o + ((q >> 2) & 1), cy + o + ((q >> 1) & 1), cz + o + (q & 1))]);
-    const uint32_t c2 =
-        onehot(socc[oidx(b, cx + 1, cy, cz)]) + onehot(socc[oidx(b, cx - 1, cy, cz)]) +
-        onehot(socc[oidx(b, cx, cy + 1, cz)]) + onehot(socc[oidx(b, cx, cy - 1, cz)]) +
-        onehot(socc[oidx(b, cx, cy, cz + 1)]) + onehot(socc[oidx(b, cx, cy, cz - 1)]);
-    Real g[8];
+    for (int q = 0; q < 8; ++q) c1 += 1u << s1[((q >> 2) & 1) + ((q >> 1) & 1) * EX + (q & 1) * (EX * EY)];
+    const uint32_t c2 = (1u << s2[1]) + (1u << s2[-1]) + (1u << s2[EX]) + (1u << s2[-EX]) +
+                        (1u << s2[EX * EY]) + (1u << s2[-EX * EY]);
+    Real g[NA];
 #pragma unroll
-    for (int A = 0; A < 8; ++A) g[A] = Real(0);
+    for (int A = 0; A < NA; ++A) g[A] = Real(0);
+#pragma unroll
     for (int s = 1; s < S; ++s) {
       const Real n1 = (Real)nib(c1, s), n2 = (Real)nib(c2, s);
 #pragma unroll
-      for (int A = 0; A < 8; ++A)
-        if (A < NA) g[A] = fma(n2, sDs2[A * S + s], fma(n1, sDs1[A * S + s], g[A]));
+      for (int A = 0; A < NA; ++A) g[A] = fma(n2, Ds2[A * S + s], fma(n1, Ds1[A * S + s], g[A]));
     }
 #pragma unroll
-    for (int A = 0; A < 8; ++A)
-      if (A < NA) sG[A * (2 * HV) + r] = g[A];
+    for (int A = 0; A < NA; ++A) sG[A * (2 * HV) + r] = g[A];
   }
   __syncthreads();
 
   // Phase 3: the 8 candidates of every brick site, from the field alone.
+  // All reads of a lane are issued before any result is needed; a target
+  // holding a vacancy reads species 0's entries and is masked afterwards.
   const Real h = Sweep<Real>::h(d);
-  for (int t = tid; t < Sh::NT; t += kSweepThreads) {
-    const int cx = t % TX;
-    const int row = t / TX;
+  for (int t = tid; t < Sh::NT * LPS; t += kSweepThreads) {
+    const int st = t / LPS, part = t % LPS;
+    const int cx = st % TX;
+    const int row = st / TX;
     const int cy = row % TY;
     const int bz = row / TY;
     const int cz = bz % TZ;
     const int b = bz / TZ;
     const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
     if (gx >= lx || gy >= ly || gz >= lz) continue;
-    const int sp = socc[oidx(b, cx, cy, cz)];
+    const int sp4 = socc[oidx(b, cx, cy, cz)];
     // Field planes are species-major (plane A holds G'_A of every region
     // site), so neighbouring lanes read neighbouring words.
     const int ip = b * HV + ((cz + b) * HY + (cy + b)) * HX + (cx + b);
     const int ij0 = (1 - b) * HV + (cz * HY + cy) * HX + cx;
-    const int o = b ? 0 : -1;
-    Real rr[8], ee[8];
+    const uint8_t *s1 = socc + oidx(1 - b, cx - 1 + b, cy - 1 + b, cz - 1 + b);
+    int a4[VW];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int c = 0; c < VW; ++c) {
+      const int k = part * VW + c;
+      a4[c] = s1[((k >> 2) & 1) + ((k >> 1) & 1) * EX + (k & 1) * (EX * EY)];
+    }
+    // Byte offsets: a brick code is 4*species, so plane A of the field
+    // starts at code * (2*HV) words and table entry [A][s] at code*S + 4*s
+    // bytes (binary32; twice that for binary64).
+    constexpr int WS = (int)sizeof(Real) / 4;
+    const unsigned char *gb = reinterpret_cast<const unsigned char *>(sG);
+    Real gpa[VW], gja[VW], cc[VW], e0a[VW], kk[VW];
+#pragma unroll
+    for (int c = 0; c < VW; ++c) {
+      const int k = part * VW + c;
       const int px = (k >> 2) & 1, py = (k >> 1) & 1, pz = k & 1;
-      const int A = socc[oidx(1 - b, cx + o + px, cy + o + py, cz + o + pz)];
-      if (A == V) {
-        rr[k] = Real(0);
-        ee[k] = inf_of<Real>();
-      } else {
-        const Real gpa = sG[A * (2 * HV) + ip];
-        const Real gja = sG[A * (2 * HV) + ij0 + (pz * HY + py) * HX + px];
-        rr[k] = Sweep<Real>::rate(sC[A * S + sp], h, gja - gpa);
-        if (WITH_EA) ee[k] = se0[A] + Real(0.5) * ((gpa - gja) + sK[A * S + sp]);
+      const int a4c = min(a4[c], 4 * (NA - 1));
+      const int plane = a4c * (2 * HV * WS);
+      gpa[c] = *reinterpret_cast<const Real *>(gb + plane + ip * (int)sizeof(Real));
+      gja[c] = *reinterpret_cast<const Real *>(gb + plane + (ij0 + (pz * HY + py) * HX + px) * (int)sizeof(Real));
+      const int tab = (a4c * S + sp4) * WS;
+      cc[c] = *reinterpret_cast<const Real *>(reinterpret_cast<const unsigned char *>(sC) + tab);
+      if (WITH_EA) {
+        e0a[c] = *reinterpret_cast<const Real *>(reinterpret_cast<const unsigned char *>(se0) + a4c * WS);
+        kk[c] = *reinterpret_cast<const Real *>(reinterpret_cast<const unsigned char *>(sK) + tab);
       }
     }
-    const int64_t site = (int64_t)b * ncell + ((int64_t)gz * ly + gy) * lx + gx;
-    Real *out = rates + site * 8;
+    vecw rr, ee;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) __builtin_nontemporal_store(rr[k], out + k);
-    if (WITH_EA) {
-      Real *oe = ea + site * 8;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) __builtin_nontemporal_store(ee[k], oe + k);
+    for (int c = 0; c < VW; ++c) {
+      const bool masked = a4[c] == 4 * V;
+      const Real r = Sweep<Real>::rate(cc[c], h, gja[c] - gpa[c]);
+      rr[c] = masked ? Real(0) : r;
+      if (WITH_EA) ee[c] = masked ? inf_of<Real>() : e0a[c] + Real(0.5) * ((gpa[c] - gja[c]) + kk[c]);
     }
+    // Site indices stay below 2^31 (checked at create).
+    const size_t site = (unsigned)(b * ncell + (gz * ly + gy) * lx + gx);
+    __builtin_nontemporal_store(rr, (vecw *)(rates + site * 8) + part);
+    if (WITH_EA) __builtin_nontemporal_store(ee, (vecw *)(ea + site * 8) + part);
   }
 }
 
@@ -303,40 +353,52 @@ hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h, const uin
   return hipGetLastError();
 }
 
-template <int TX, int TY, int TZ, class Real>
+template <int TX, int TY, int TZ, int S, class Real>
 static hipError_t launch_sweep(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                                void *rates, void *ea, hipStream_t stream) {
   using Sh = SweepShape<TX, TY, TZ>;
   const unsigned tiles = (unsigned)(((h.lx + TX - 1) / TX) * ((h.ly + TY - 1) / TY) *
                                     ((h.lz + TZ - 1) / TZ));
-  const size_t lds = Sh::lds_bytes(h.S, sizeof(Real));
-  if (ea) {
-    auto k = k_rates_all<TX, TY, TZ, Real, true>;
-    if (lds > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k, dim3(tiles), dim3(kSweepThreads), lds, stream, d_desc, occ, (Real *)rates, (Real *)ea);
-  } else {
-    auto k = k_rates_all<TX, TY, TZ, Real, false>;
-    if (lds > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL(k, dim3(tiles), dim3(kSweepThreads), lds, stream, d_desc, occ, (Real *)rates, (Real *)ea);
+  const size_t lds = Sh::lds_bytes(S, sizeof(Real));
+  auto k = ea ? k_rates_all<TX, TY, TZ, S, Real, true> : k_rates_all<TX, TY, TZ, S, Real, false>;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
   }
+  hipLaunchKernelGGL(k, dim3(tiles), dim3(kSweepThreads), lds, stream, d_desc, occ, (Real *)rates,
+                     (Real *)ea);
   return hipGetLastError();
+}
+
+template <int S, class Real>
+static hipError_t launch_sweep_s(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
+                                 void *rates, void *ea, hipStream_t stream) {
+  // The field holds S-1 values per region site: binary64 and many species
+  // take the narrower brick so that several workgroups share a CU.
+  if (sizeof(Real) == 4 && S <= 5)
+    return launch_sweep<32, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
+  return launch_sweep<16, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
+}
+
+template <class Real>
+static hipError_t launch_sweep_r(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
+                                 void *rates, void *ea, hipStream_t stream) {
+  switch (h.S) {
+    case 2: return launch_sweep_s<2, Real>(d_desc, h, occ, rates, ea, stream);
+    case 3: return launch_sweep_s<3, Real>(d_desc, h, occ, rates, ea, stream);
+    case 4: return launch_sweep_s<4, Real>(d_desc, h, occ, rates, ea, stream);
+    case 5: return launch_sweep_s<5, Real>(d_desc, h, occ, rates, ea, stream);
+    case 6: return launch_sweep_s<6, Real>(d_desc, h, occ, rates, ea, stream);
+    case 7: return launch_sweep_s<7, Real>(d_desc, h, occ, rates, ea, stream);
+    case 8: return launch_sweep_s<8, Real>(d_desc, h, occ, rates, ea, stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                             int precision, void *rates, void *ea, hipStream_t stream) {
-  // The field holds S-1 values per region site: narrow the brick for many species.
-  if (h.S <= 5) {
-    if (precision == AKMC_FP32) return launch_sweep<32, 4, 4, float>(d_desc, h, occ, rates, ea, stream);
-    return launch_sweep<32, 4, 4, double>(d_desc, h, occ, rates, ea, stream);
-  }
-  if (precision == AKMC_FP32) return launch_sweep<16, 4, 4, float>(d_desc, h, occ, rates, ea, stream);
-  return launch_sweep<16, 4, 4, double>(d_desc, h, occ, rates, ea, stream);
+  if (precision == AKMC_FP32) return launch_sweep_r<float>(d_desc, h, occ, rates, ea, stream);
+  return launch_sweep_r<double>(d_desc, h, occ, rates, ea, stream);
 }
 
 }  // namespace akmc
