@@ -120,9 +120,22 @@ template <class Real>
 __device__ __forceinline__ Real delta_e_counts(uint32_t c1i, uint32_t c1j, uint32_t c2i,
                                                uint32_t c2j, const Real *D1row,
                                                const Real *D2row, int S) {
+  // All 16 table entries are read before the chain starts (entries past S
+  // belong to the next row or the padding of the 64-entry tables and are
+  // not used), so the reads overlap instead of paying one latency each.
+  Real d1[8], d2[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    d1[s] = D1row[s];
+    d2[s] = D2row[s];
+  }
   Real acc = Real(0);
-  for (int s = 0; s < S; ++s) acc = fma((Real)(nib(c1i, s) - nib(c1j, s)), D1row[s], acc);
-  for (int s = 0; s < S; ++s) acc = fma((Real)(nib(c2i, s) - nib(c2j, s)), D2row[s], acc);
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+    if (s < S) acc = fma((Real)(nib(c1i, s) - nib(c1j, s)), d1[s], acc);
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+    if (s < S) acc = fma((Real)(nib(c2i, s) - nib(c2j, s)), d2[s], acc);
   return acc;
 }
 

@@ -617,8 +617,12 @@ struct Runner {
         l -= 1;
       }
       const int v = node >> 3, k = node & 7;
-      const int A = s.spec[v * 8 + k];
-      const int pp = s.pos[v];
+      int A = s.spec[v * 8 + k];
+      int pp = s.pos[v];
+      if (G == 64) {  // one lattice per wavefront: keep the event's scalars in SGPRs
+        A = __builtin_amdgcn_readfirstlane(A);
+        pp = __builtin_amdgcn_readfirstlane(pp);
+      }
       const int X = pos_x(pp), Y = pos_y(pp), Z = pos_z(pp);
       const int JX = wrapc(X + dir_sx(k), g.X2), JY = wrapc(Y + dir_sy(k), g.Y2),
                 JZ = wrapc(Z + dir_sz(k), g.Z2);
@@ -641,10 +645,12 @@ struct Runner {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       // Footprint of the moved vacancy around its new site j, gathered
       // before the swap is stored; the two swapped sites are patched below.
-      int site0[8];
-      uint8_t val0[8];
+      // Box 0 holds elements 0 .. kFootN-1, i.e. the first M0 of this lane.
+      constexpr int M0 = (kFootN + G - 1) / G;
+      int site0[M0];
+      uint8_t val0[M0];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
+      for (int m = 0; m < M0; ++m) {
         const int f = foot[m];
         site0[m] = -1;
         val0[m] = (uint8_t)V;
@@ -660,7 +666,6 @@ struct Runner {
         occ[sj] = (uint8_t)V;
         if (ev) *ev = rec;
       }
-      gsync();
       if (gl == 0) s.pos[v] = pack_pos(JX, JY, JZ);
       gsync();
 
@@ -669,15 +674,16 @@ struct Runner {
       if (full) {
         na = nv;
       } else {
-        na = 0;
-        for (int b0 = 0; b0 < nv; b0 += 4 * G) {
+        // Usually only v itself is that close: one ballot per 4G slots
+        // decides, and the ordered list is built only when another slot
+        // is affected.
+        auto hits = [&](int b0, bool (&hit)[4]) {
           int qp[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int vv = b0 + u * G + gl;
             qp[u] = vv < nv ? s.pos[vv] : -1;
           }
-          bool hit[4];
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             int dx = abs(pos_x(qp[u]) - X), dy = abs(pos_y(qp[u]) - Y), dz = abs(pos_z(qp[u]) - Z);
@@ -686,14 +692,36 @@ struct Runner {
             dz = min(dz, g.Z2 - dz);
             hit[u] = qp[u] >= 0 && max(dx, max(dy, dz)) <= 4;
           }
+        };
+        bool others = false;
+        for (int b0 = 0; b0 < nv; b0 += 4 * G) {
+          bool hit[4];
+          hits(b0, hit);
+          bool oth = false;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const uint64_t m = gp.ballot(hit[u]);
-            if (hit[u]) s.aff[na + __popcll(m & gp.lanes_below())] = b0 + u * G + gl;
-            na += __popcll(m);
-          }
+          for (int u = 0; u < 4; ++u) oth = oth || (hit[u] && b0 + u * G + gl != v);
+          others = others || gp.ballot(oth) != 0;
         }
-        gsync();
+        if (!others) {
+          na = 1;
+          if (MLP) {
+            if (gl == 0) s.aff[0] = v;
+            gsync();
+          }
+        } else {
+          na = 0;
+          for (int b0 = 0; b0 < nv; b0 += 4 * G) {
+            bool hit[4];
+            hits(b0, hit);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const uint64_t m = gp.ballot(hit[u]);
+              if (hit[u]) s.aff[na + __popcll(m & gp.lanes_below())] = b0 + u * G + gl;
+              na += __popcll(m);
+            }
+          }
+          gsync();
+        }
       }
       t += dt;
       dig = fnv_event(dig, n, si, sj);
@@ -702,7 +730,7 @@ struct Runner {
       if (!MLP && na == 1) {
         // Only the moved vacancy: its box is already gathered.
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int m = 0; m < M0; ++m) {
           const int f = foot[m];
           if (f < 0 || ((f >> 18) & 63) != 0) continue;
           uint8_t v8 = val0[m];
