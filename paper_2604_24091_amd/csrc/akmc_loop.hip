@@ -558,9 +558,17 @@ struct Runner {
       // it.  A full wavefront takes two levels per LDS round trip (lane
       // 8c + c' looks at grandchild c' of child c); the comparisons and
       // subtractions are the same, so the result does not depend on G.
+      // The level loop is unrolled at compile time so that every level's
+      // offsets are constants and the descent stays in scalar registers.
       int node = 0;
-      int l = nlev;
-      while (l >= 0) {
+      bool skip = false;
+#pragma unroll
+      for (int l = kMaxLevels; l >= 0; --l) {
+        if (l > nlev) continue;
+        if (skip) {
+          skip = false;
+          continue;
+        }
         const int base = (l == nlev) ? 0 : node * 8;
         if (G == 64 && l >= 1) {
           const int c = gl >> 3, c2 = gl & 7;
@@ -584,13 +592,12 @@ struct Runner {
               const double qbp = lane_value(qb, 8 * cs + (cb > 0 ? cb - 1 : 0));
               tgt = cb > 0 ? t1u - qbp : t1u;
               node = 8 * (base + cs) + cb;
-              l -= 2;
+              skip = true;
             } else {
-              // No grandchild exceeds the target (rounding): the single
-              // step below takes level l-1's fallback.
+              // No grandchild exceeds the target (rounding): level l-1
+              // takes the single step below with its fallback.
               tgt = t1u;
               node = base + cs;
-              l -= 1;
             }
             continue;
           }
@@ -614,7 +621,6 @@ struct Runner {
         const double prev = lane_value(qv, c > 0 ? c - 1 : 0);
         if (c > 0) tgt = tgt - prev;
         node = base + c;
-        l -= 1;
       }
       const int v = node >> 3, k = node & 7;
       int A = s.spec[v * 8 + k];
