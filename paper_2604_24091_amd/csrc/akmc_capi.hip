@@ -96,16 +96,16 @@ LatDesc make_desc(const akmc_params *p, int nv) {
     for (int s = 0; s < S; ++s) {
       const double d1 = p->eps1[A * S + s] - p->eps1[V * S + s];
       const double d2 = p->eps2[A * S + s] - p->eps2[V * S + s];
-      d.D1[A * S + s] = d1;
-      d.D2[A * S + s] = d2;
-      d.D1f[A * S + s] = (float)d1;
-      d.D2f[A * S + s] = (float)d2;
+      d.D1[A * 8 + s] = d1;
+      d.D2[A * 8 + s] = d2;
+      d.D1f[A * 8 + s] = (float)d1;
+      d.D2f[A * 8 + s] = (float)d2;
     }
   for (int A = 0; A < S; ++A)
     for (int s = 0; s < S; ++s) {
-      const double s1 = d.D1[A * S + s] - d.D1[A * S + 0];
-      const double s2 = d.D2[A * S + s] - d.D2[A * S + 0];
-      const double kk = d.D1[A * S + s] - d.D1[A * S + A];
+      const double s1 = d.D1[A * 8 + s] - d.D1[A * 8 + 0];
+      const double s2 = d.D2[A * 8 + s] - d.D2[A * 8 + 0];
+      const double kk = d.D1[A * 8 + s] - d.D1[A * 8 + A];
       d.Ds1[A * S + s] = s1; d.Ds2[A * S + s] = s2; d.K[A * S + s] = kk;
       d.Ds1f[A * S + s] = (float)s1; d.Ds2f[A * S + s] = (float)s2; d.Kf[A * S + s] = (float)kk;
     }

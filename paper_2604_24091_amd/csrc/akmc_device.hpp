@@ -110,32 +110,40 @@ __device__ __forceinline__ uint64_t fnv_event(uint64_t h, int64_t n, int32_t fro
 // code); a shell has at most 8 members, so no nibble overflows.
 __device__ __forceinline__ uint32_t onehot(int s) { return 1u << (4 * s); }
 __device__ __forceinline__ int nib(uint32_t c, int s) { return (int)((c >> (4 * s)) & 15u); }
+// Nibble s of c read as a 4-bit two's complement number.
+__device__ __forceinline__ int nib_signed(uint32_t c, int s) {
+  return (int)(c << (28 - 4 * s)) >> 28;
+}
 
 // Energy change from the bond counts, as one fused multiply-add chain over
 // species codes, shell 1 first:  dE = sum_s dn1[s] D1[A][s] + dn2[s] D2[A][s]
 // with dn1 = c1i - c1j (first shells of i without j and of j without i)
 // and dn2 = c2i - c2j (second shells).  The counts are exact integers, so
 // any way of gathering them gives the same bits.
+//
+// Rows hold 8 entries, zero past the species count: the extra terms are
+// fma(0, 0, acc) = acc exactly (acc starts at +0 and is never -0), so the
+// chain equals the one over s < S.  Every count nibble is at most 7 (7 or 6
+// sites per group), so 8 + ci - cj stays within a nibble and one subtraction
+// serves all species; xor with 8 turns each nibble into the 4-bit two's
+// complement of dn.
 template <class Real>
 __device__ __forceinline__ Real delta_e_counts(uint32_t c1i, uint32_t c1j, uint32_t c2i,
                                                uint32_t c2j, const Real *D1row,
-                                               const Real *D2row, int S) {
-  // All 16 table entries are read before the chain starts (entries past S
-  // belong to the next row or the padding of the 64-entry tables and are
-  // not used), so the reads overlap instead of paying one latency each.
+                                               const Real *D2row) {
   Real d1[8], d2[8];
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     d1[s] = D1row[s];
     d2[s] = D2row[s];
   }
+  const uint32_t e1 = ((c1i + 0x88888888u) - c1j) ^ 0x88888888u;
+  const uint32_t e2 = ((c2i + 0x88888888u) - c2j) ^ 0x88888888u;
   Real acc = Real(0);
 #pragma unroll
-  for (int s = 0; s < 8; ++s)
-    if (s < S) acc = fma((Real)(nib(c1i, s) - nib(c1j, s)), d1[s], acc);
+  for (int s = 0; s < 8; ++s) acc = fma((Real)nib_signed(e1, s), d1[s], acc);
 #pragma unroll
-  for (int s = 0; s < 8; ++s)
-    if (s < S) acc = fma((Real)(nib(c2i, s) - nib(c2j, s)), d2[s], acc);
+  for (int s = 0; s < 8; ++s) acc = fma((Real)nib_signed(e2, s), d2[s], acc);
   return acc;
 }
 

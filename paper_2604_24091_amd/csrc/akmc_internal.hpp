@@ -20,7 +20,7 @@ struct LatDesc {
   int64_t occ_off;            // byte offset of the occupancy in the occupancy arena
   int64_t slot_off;           // element offset in the slot arena
   uint64_t seed, stream;
-  double D1[64], D2[64];      // row A: D_k[A][0..S-1]
+  double D1[64], D2[64];      // row A at 8*A: D_k[A][0..S-1], zero for s >= S
   double e0[8];
   double nu, kT;              // kT = kb*T in binary64
   float D1f[64], D2f[64];

@@ -130,32 +130,33 @@ __device__ __forceinline__ Lds<Real> carve(unsigned char *base, const GroupLayou
   return s;
 }
 
-// Rate of candidate k of the vacancy whose footprint sits in `box`.  Bond
-// counts as in the site-list kernel: N1(i) without j, N1(j) without i,
-// N2(i), N2(j).  Returns the rate widened to binary64 and the target species.
+// Rate of candidate k of the vacancy whose footprint sits in `box`.  Boxes
+// hold 4*species (the shift of that species' count nibble).  Bond counts as
+// in the site-list kernel: N1(i) without j, N1(j) without i, N2(i), N2(j).
+// Returns the rate widened to binary64 and the target species.
 template <class Real>
-__device__ __forceinline__ double eval_box(const uint8_t *box, int k, int S, const Real *D1,
+__device__ __forceinline__ double eval_box(const uint8_t *box, int k, int V, const Real *D1,
                                            const Real *D2, const Real *e0, Real nu, Real kT,
                                            int &A_out) {
-  const int V = S - 1;
   const int jb = kBoxC + dir_sx(k) + 7 * dir_sy(k) + 49 * dir_sz(k);
-  const int A = box[jb];
+  const int a4 = box[jb];
+  const int A = a4 >> 2;
   A_out = A;
   if (A == V) return 0.0;
   uint32_t c1i = 0, c1j = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const int off = dir_sx(q) + 7 * dir_sy(q) + 49 * dir_sz(q);
-    c1i += onehot(box[kBoxC + off]);
-    c1j += onehot(box[jb + off]);
+    c1i += 1u << box[kBoxC + off];
+    c1j += 1u << box[jb + off];
   }
-  const uint32_t c2i = onehot(box[kBoxC + 2]) + onehot(box[kBoxC - 2]) + onehot(box[kBoxC + 14]) +
-                       onehot(box[kBoxC - 14]) + onehot(box[kBoxC + 98]) + onehot(box[kBoxC - 98]);
-  const uint32_t c2j = onehot(box[jb + 2]) + onehot(box[jb - 2]) + onehot(box[jb + 14]) +
-                       onehot(box[jb - 14]) + onehot(box[jb + 98]) + onehot(box[jb - 98]);
-  c1i -= onehot(A);
-  c1j -= onehot(box[kBoxC]);
-  const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, D1 + A * S, D2 + A * S, S);
+  const uint32_t c2i = (1u << box[kBoxC + 2]) + (1u << box[kBoxC - 2]) + (1u << box[kBoxC + 14]) +
+                       (1u << box[kBoxC - 14]) + (1u << box[kBoxC + 98]) + (1u << box[kBoxC - 98]);
+  const uint32_t c2j = (1u << box[jb + 2]) + (1u << box[jb - 2]) + (1u << box[jb + 14]) +
+                       (1u << box[jb - 14]) + (1u << box[jb + 98]) + (1u << box[jb - 98]);
+  c1i -= 1u << a4;
+  c1j -= 1u << box[kBoxC];
+  const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, D1 + 8 * A, D2 + 8 * A);
   const Real ea = e0[A] + Real(0.5) * de;
   return (double)rate_from_barrier(ea, nu, kT);
 }
@@ -323,7 +324,7 @@ struct Runner {
       vv = s.aff[p0 + q];
       const int flip = (~k) & 7;
       const int jb = kBoxC + dir_sx(k) + 7 * dir_sy(k) + 49 * dir_sz(k);
-      A = box[jb];
+      A = box[jb] >> 2;
       uint8_t *row = ml.senv + gp.gl * 32;
       row[0] = (uint8_t)A;
       uint32_t c1i = 0, c1j = 0, c2i = 0, c2j = 0;
@@ -331,7 +332,7 @@ struct Runner {
       for (int d2 = 0; d2 < 8; ++d2) {
         const int qq = d2 ^ flip;
         const int off = dir_sx(qq) + 7 * dir_sy(qq) + 49 * dir_sz(qq);
-        const uint8_t si = box[kBoxC + off], sj = box[jb + off];
+        const uint8_t si = box[kBoxC + off] >> 2, sj = box[jb + off] >> 2;
         if (d2 < 7) { row[1 + d2] = si; c1i += onehot(si); }
         if (d2 > 0) { row[13 + d2] = sj; c1j += onehot(sj); }
       }
@@ -340,7 +341,7 @@ struct Runner {
         const int axis = m >> 1;
         const int mm = ((flip >> (2 - axis)) & 1) ? (m ^ 1) : m;
         const int off = ((mm & 1) ? -1 : 1) * (axis == 0 ? 2 : axis == 1 ? 14 : 98);
-        const uint8_t si = box[kBoxC + off], sj = box[jb + off];
+        const uint8_t si = box[kBoxC + off] >> 2, sj = box[jb + off] >> 2;
         row[8 + m] = si;
         row[21 + m] = sj;
         c2i += onehot(si);
@@ -349,7 +350,7 @@ struct Runner {
       if (A != V) {
         // N1(i) without j does not contain the moving atom's site; the box
         // centre (the vacancy) is not part of N1(j) without i.
-        const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, s.D1 + A * S, s.D2 + A * S, S);
+        const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, s.D1 + 8 * A, s.D2 + 8 * A);
         ea_pair = (float)(s.e0[A] + Real(0.5) * de);
         ood = ml.ood[32 + A] < 1;  // moving species never seen in training
         for (int sp = 0; sp < S; ++sp)
@@ -417,7 +418,7 @@ struct Runner {
         uint8_t v8 = val[m];
         if (site[m] == si) v8 = (uint8_t)a_new;
         else if (site[m] == sj) v8 = (uint8_t)V;
-        s.box[((f >> 18) & 63) * kBoxBytes + (f & 511)] = v8;
+        s.box[((f >> 18) & 63) * kBoxBytes + (f & 511)] = (uint8_t)(v8 << 2);
       }
       gsync();
       const int q = gp.gl >> 3, k = gp.gl & 7;
@@ -427,7 +428,7 @@ struct Runner {
         if (q < np) {
           vv = s.aff[p0 + q];
           int A;
-          r = eval_box<Real>(s.box + q * kBoxBytes, k, S, s.D1, s.D2, s.e0, nu, kT, A);
+          r = eval_box<Real>(s.box + q * kBoxBytes, k, V, s.D1, s.D2, s.e0, nu, kT, A);
           s.spec[vv * 8 + k] = (uint8_t)A;
         }
       } else {
@@ -539,16 +540,23 @@ struct Runner {
     double gtot = gamma_tot();
     frozen = !(gtot > 0.0);
 
+    double ru1v = 0.0, rwv = 0.0;
     for (int64_t e = 0; e < a.n_events && !frozen; ++e) {
       const int ce = (int)(e % G);
       if (ce == 0) {
         double u1, u2;
         event_uniforms(seed, stream, n + gl, u1, u2);
-        s.ru1[gl] = u1;
-        s.rw[gl] = -log(u2);
-        gsync();
+        if (G == 64) {  // lane c keeps event c's pair in registers
+          ru1v = u1;
+          rwv = -log(u2);
+        } else {
+          s.ru1[gl] = u1;
+          s.rw[gl] = -log(u2);
+          gsync();
+        }
       }
-      const double u1 = s.ru1[ce], w = s.rw[ce];
+      const double u1 = G == 64 ? lane_value(ru1v, ce) : s.ru1[ce];
+      const double w = G == 64 ? lane_value(rwv, ce) : s.rw[ce];
       double tgt = u1 * gtot;
 
       // Selection: descend the tree of partial sums.  Levels nlev..1 hold
@@ -743,14 +751,14 @@ struct Runner {
           if (f & (1 << 24)) v8 = (uint8_t)V;
           else if (site0[m] == si) v8 = (uint8_t)A;
           else if (site0[m] == sj) v8 = (uint8_t)V;
-          s.box[f & 511] = v8;
+          s.box[f & 511] = (uint8_t)(v8 << 2);
         }
         gsync();
         const int kk = gl & 7;
         double r = 0.0;
         if (gl < 8) {
           int Ak;
-          r = eval_box<Real>(s.box, kk, S, s.D1, s.D2, s.e0, nu, kT, Ak);
+          r = eval_box<Real>(s.box, kk, V, s.D1, s.D2, s.e0, nu, kT, Ak);
           s.spec[v * 8 + kk] = (uint8_t)Ak;
         }
         const double pfx = subgroup_prefix(r, kk);

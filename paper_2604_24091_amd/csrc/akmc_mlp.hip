@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_env_encode(const LatDesc *__restrict__ 
     if (A == V) {
       ea[c] = __builtin_huge_valf();
     } else {
-      const double de = delta_e_counts<double>(c1i, c1j, c2i, c2j, sD1 + A * S, sD2 + A * S, S);
+      const double de = delta_e_counts<double>(c1i, c1j, c2i, c2j, sD1 + 8 * A, sD2 + 8 * A);
       ea[c] = (float)(se0[A] + 0.5 * de);
     }
   }

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
     }
     c1i -= onehot(A);           // N1(i) without j
     c1j -= onehot(occ[i]);      // N1(j) without i
-    const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, sD1 + A * S, sD2 + A * S, S);
+    const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, sD1 + 8 * A, sD2 + 8 * A);
     e = se0[A] + Real(0.5) * de;
     r = rate_from_barrier(e, Tab<Real>::nu(d), Tab<Real>::kT(d));
   }
