@@ -280,11 +280,12 @@ struct Runner {
     return __shfl(x, gp.base + src, 64);
   }
 
-  // Re-sums the tree path above one refreshed slot v: every level's node
-  // values are read up front, the one node on the path takes the value just
-  // computed below it, and each level's partials come from subgroup_prefix.
-  // Returns Gamma_tot.
-  __device__ double update_path(int v) {
+  // Re-sums the tree path above one refreshed slot v whose new total is
+  // gv: every level's node values are read up front (a lane with nothing to
+  // read loads a valid dummy and drops it, so no branch is taken), the one
+  // node on the path takes the value just computed below it, and each
+  // level's partials come from subgroup_prefix.  Returns Gamma_tot.
+  __device__ double update_path(int v, double gv) {
     const int c = gp.gl & 7;
     const bool worker = gp.gl < 8;
     double x[kMaxLevels + 1];
@@ -293,15 +294,24 @@ struct Runner {
       x[l] = 0.0;
       if (l <= nlev) {
         const int u = 8 * (v >> (3 * l)) + c;
-        if (worker && u < nl(l)) x[l] = node_value(l, u);
+        const bool ok = worker && u < nl(l);
+        const int uu = ok ? u : 0;
+        double val;
+        if (l == 1) {
+          val = s.part[uu * 8 + 7];
+        } else {
+          const int cnt = min(8, nl(l - 1) - 8 * uu);
+          val = Q(l - 1)[8 * uu + cnt - 1];
+        }
+        x[l] = ok ? val : 0.0;
       }
     }
-    double fresh = 0.0;
+    double fresh = gv;
 #pragma unroll
     for (int l = 1; l <= kMaxLevels; ++l) {
       if (l <= nlev) {
         const int g = v >> (3 * l);
-        if (l > 1 && c == ((v >> (3 * (l - 1))) & 7)) x[l] = fresh;
+        if (c == ((v >> (3 * (l - 1))) & 7)) x[l] = fresh;
         const double pfx = subgroup_prefix(x[l], c);
         const int cnt = min(8, nl(l) - 8 * g);
         if (worker && c < cnt) Q(l)[8 * g + c] = pfx;
@@ -763,8 +773,7 @@ struct Runner {
         }
         const double pfx = subgroup_prefix(r, kk);
         if (gl < 8) s.part[v * 8 + kk] = pfx;
-        gsync();
-        gtot = update_path(v);
+        gtot = update_path(v, lane_value(pfx, 7));
       } else {
         refresh(na, si, sj, A, false, nullptr, rec);
         update_tree(na);
