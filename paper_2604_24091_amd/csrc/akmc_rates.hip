@@ -115,19 +115,25 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
 // ---------------------------------------------------------- bulk sweep
 
 template <class Real> struct Sweep;
+// The rate of candidate p <- j as one exponential of the sum of a per-site
+// term and a per-target term (see k_rates_all):
+//   binary64:  ln r    = (Cn[A][s_p]  - h G'_A(p)) + h G'_{s_j}(j),  h = beta/2
+//   binary32:  log2 r  = (C2f[A][s_p] - h G'_A(p)) + h G'_{s_j}(j),  h = (beta/2) log2(e)
 template <> struct Sweep<double> {
-  // ln r = Cn[A][s_p] + (beta/2) dG;  r = exp(ln r)
-  __device__ static double C(const LatDesc *d, int i) { return d->Cn[i]; }
   __device__ static double h(const LatDesc *d) { return d->half_beta; }
-  __device__ static double rate(double c, double h, double dg) { return exp(fma(h, dg, c)); }
+  __device__ static double table(const LatDesc *d, int i) { return d->Cn[i]; }
+  __device__ static double target(double h, double H) { return h * H; }
+  __device__ static double site(double c, double h, double g) { return c - h * g; }
+  __device__ static double masked_site() { return -__builtin_huge_val(); }
+  __device__ static double rate(double t, double e) { return exp(t + e); }
 };
 template <> struct Sweep<float> {
-  // log2 r = C2f[A][s_p] + h2f dG;  r = 2^(log2 r), one hardware exponential
-  __device__ static float C(const LatDesc *d, int i) { return d->C2f[i]; }
   __device__ static float h(const LatDesc *d) { return d->h2f; }
-  __device__ static float rate(float c, float h, float dg) {
-    return __builtin_amdgcn_exp2f(fmaf(h, dg, c));
-  }
+  __device__ static float table(const LatDesc *d, int i) { return d->C2f[i]; }
+  __device__ static float target(float h, float H) { return h * H; }
+  __device__ static float site(float c, float h, float g) { return c - h * g; }
+  __device__ static float masked_site() { return -__builtin_huge_valf(); }
+  __device__ static float rate(float t, float e) { return __builtin_amdgcn_exp2f(t + e); }
 };
 
 constexpr int kSweepThreads = 256;
@@ -142,45 +148,66 @@ struct SweepShape {
   static constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, HV = HX * HY * HZ;  // field region
   static constexpr int NT = 2 * TX * TY * TZ;                                     // brick sites
   static constexpr int OCC_BYTES = (2 * EV + 15) & ~15;
-  static size_t lds_bytes(int S, size_t real) {
-    return OCC_BYTES + (size_t)2 * HV * (size_t)(S - 1) * real;
+  // per region site: bond counts (2 words), the target term, the field
+  // (barrier output only); site terms: binary32 per lane (S planes of 256),
+  // binary64 per brick site (S-1 planes of NT, twice with the barrier output)
+  __host__ __device__ static constexpr size_t terms(int S, size_t real, bool with_ea) {
+    return real == 4 ? (size_t)S * kSweepThreads : (size_t)(S - 1) * NT * (with_ea ? 2 : 1);
+  }
+  static size_t lds_bytes(int S, size_t real, bool with_ea) {
+    return OCC_BYTES + (size_t)2 * HV * (8 + real + (with_ea ? real : 0)) +
+           terms(S, real, with_ea) * real;
   }
 };
 
-// Region layout of the field G'_A: corners (b = 0) at cells [0, T+1) and
-// centres (b = 1) at cells [-1, T) of the brick, each stored at index
-// h = c + b.  The targets of a corner at cell c are the centres at cells
-// c - 1 + [s > 0], those of a centre the corners at c + [s > 0]; both sit
-// at index h = c + [s > 0] of the other sublattice.
+// Region layout: corners (b = 0) at cells [0, T+1) and centres (b = 1) at
+// cells [-1, T) of the brick, each stored at index h = c + b.  The targets
+// of a corner at cell c are the centres at cells c - 1 + [s > 0], those of
+// a centre the corners at c + [s > 0]; both sit at index h = c + [s > 0] of
+// the other sublattice.
 //
-// Output: LPS lanes share a site, each writing 16 contiguous bytes (CPL
-// candidates), so one store instruction of a wavefront covers a
-// contiguous kilobyte of the rate array.
+// With the field G'_A(q) = sum_s n1_s(q) Ds1[A][s] + n2_s(q) Ds2[A][s], the
+// rate of p <- j (species A = s_j) is, in logarithms,
+//   ln r = Cn[A][s_p] - h G'_A(p) + h G'_A(j),
+// and a target enters only with its own species (A = s_j).  Phase 2 stores
+// per region site its counts and its target term; phase 3 forms per brick
+// site the term of every mover species (a per-lane table in LDS, whose
+// entry for the vacancy code gives a zero rate) and combines it with the
+// target terms of the 8 neighbours.
+//
+// Output: one lane per site writes its 8 rates as two (binary32) or four
+// (binary64) 16-byte non-temporal vectors; neighbouring lanes write
+// neighbouring 32- or 64-byte rows.
 template <int TX, int TY, int TZ, int S, class Real, bool WITH_EA>
 __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__restrict__ d,
                                                              const uint8_t *__restrict__ occ,
                                                              Real *__restrict__ rates,
                                                              Real *__restrict__ ea) {
   using Sh = SweepShape<TX, TY, TZ>;
+  using SW = Sweep<Real>;
   constexpr int EX = Sh::EX, EY = Sh::EY, EZ = Sh::EZ, EV = Sh::EV, PX = Sh::PX;
   constexpr int HX = Sh::HX, HY = Sh::HY, HV = Sh::HV;
   constexpr int V = S - 1, NA = S - 1;
   constexpr int VW = 16 / (int)sizeof(Real);  // candidates per 16-byte store
-  constexpr int LPS = 8 / VW;                 // lanes per site
   typedef Real vecw __attribute__((ext_vector_type(VW)));
   extern __shared__ __align__(16) unsigned char sweep_lds[];
   uint8_t *socc = sweep_lds;
-  Real *sG = (Real *)(sweep_lds + Sh::OCC_BYTES);
-  __shared__ Real sC[64], se0[8], sK[64];
+  uint2 *sCnt = (uint2 *)(sweep_lds + Sh::OCC_BYTES);
+  Real *sE = (Real *)(sCnt + 2 * HV);
+  Real *sT = sE + 2 * HV;              // site terms
+  Real *sH = sT + Sh::terms(S, sizeof(Real), WITH_EA);  // WITH_EA only
+  __shared__ Real sC[64], sDs1[64], sDs2[64], se0[8], sK[64];
 
   const int tid = threadIdx.x;
   const int lx = d->lx, ly = d->ly, lz = d->lz;
   const int ncell = lx * ly * lz;
   if (tid < 64) {
-    sC[tid] = Sweep<Real>::C(d, tid);
-    sK[tid] = Tab<Real>::K(d)[tid];
+    sC[tid] = SW::table(d, tid);
+    sDs1[tid] = Tab<Real>::Ds1(d)[tid];
+    sDs2[tid] = Tab<Real>::Ds2(d)[tid];
+    if (WITH_EA) sK[tid] = Tab<Real>::K(d)[tid];
   }
-  if (tid < 8) se0[tid] = Tab<Real>::e0(d)[tid];
+  if (WITH_EA && tid < 8) se0[tid] = Tab<Real>::e0(d)[tid];
 
   const int ntx = (lx + TX - 1) / TX, nty = (ly + TY - 1) / TY;
   const int tile = blockIdx.x;
@@ -188,10 +215,11 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
   const int y0 = ((tile / ntx) % nty) * TY;
   const int z0 = (tile / (ntx * nty)) * TZ;
 
-  // Phase 1: occupancy brick of both sublattices.  One conditional wrap per
-  // axis suffices when every edge exceeds the brick (then x is staged in
-  // aligned dwords if lx is a multiple of 4); small lattices take the
-  // general modulo byte by byte.
+  // Phase 1: occupancy brick of both sublattices, as 4*species (the shift of
+  // that species' count nibble).  One conditional wrap per axis suffices
+  // when every edge exceeds the brick (then x is staged in aligned dwords if
+  // lx is a multiple of 4); small lattices take the general modulo byte by
+  // byte.
   const bool simple = lx > TX + 2 && ly > TY + 2 && lz > TZ + 2;
   if (simple && (lx & 3) == 0) {
     // 16 lanes per brick row (DW <= 16 dwords used), rows in pow-2 strides.
@@ -237,12 +265,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
   auto oidx = [&](int b, int cx, int cy, int cz) {
     return b * EV + ((cz + 2) * EY + (cy + 2)) * EX + (cx + PX);
   };
+  const Real h = SW::h(d);
 
-  // Phase 2: G'_A(q) for every mover species A at every region site:
-  //   G'_A(q) = sum_s n1_s(q) Ds1[A][s] + n2_s(q) Ds2[A][s]   (s = 0 drops out)
-  // The brick holds 4*species, the shift of that species' count nibble.
-  // The tables are uniform over the grid and stay in scalar registers.
-  const Real *Ds1 = Tab<Real>::Ds1(d), *Ds2 = Tab<Real>::Ds2(d);
+  // Phase 2: for every region site q the bond counts (kept for the vacancy
+  // role) and the target term from the field of q's own species.
   for (int r = tid; r < 2 * HV; r += kSweepThreads) {
     const int hx = r % HX;
     const int row = r / HX;
@@ -260,79 +286,143 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
     for (int q = 0; q < 8; ++q) c1 += 1u << s1[((q >> 2) & 1) + ((q >> 1) & 1) * EX + (q & 1) * (EX * EY)];
     const uint32_t c2 = (1u << s2[1]) + (1u << s2[-1]) + (1u << s2[EX]) + (1u << s2[-EX]) +
                         (1u << s2[EX * EY]) + (1u << s2[-EX * EY]);
-    Real g[NA];
+    sCnt[r] = make_uint2(c1, c2);
+    // A vacancy is never a target: its entry is computed for a mover, unused.
+    const int A = min((int)s2[0] >> 2, NA - 1);
+    Real g = Real(0);
 #pragma unroll
-    for (int A = 0; A < NA; ++A) g[A] = Real(0);
-#pragma unroll
-    for (int s = 1; s < S; ++s) {
-      const Real n1 = (Real)nib(c1, s), n2 = (Real)nib(c2, s);
-#pragma unroll
-      for (int A = 0; A < NA; ++A) g[A] = fma(n2, Ds2[A * S + s], fma(n1, Ds1[A * S + s], g[A]));
-    }
-#pragma unroll
-    for (int A = 0; A < NA; ++A) sG[A * (2 * HV) + r] = g[A];
+    for (int s = 1; s < S; ++s)
+      g = fma((Real)nib(c2, s), sDs2[A * S + s], fma((Real)nib(c1, s), sDs1[A * S + s], g));
+    sE[r] = SW::target(h, g);
+    if (WITH_EA) sH[r] = g;
   }
   __syncthreads();
 
-  // Phase 3: the 8 candidates of every brick site, from the field alone.
-  // All reads of a lane are issued before any result is needed; a target
-  // holding a vacancy reads species 0's entries and is masked afterwards.
-  const Real h = Sweep<Real>::h(d);
-  for (int t = tid; t < Sh::NT * LPS; t += kSweepThreads) {
-    const int st = t / LPS, part = t % LPS;
-    const int cx = st % TX;
-    const int row = st / TX;
+  // Phase 3: the 8 candidates of every brick site.  The field of the
+  // vacancy site for every mover species comes from its counts, with the
+  // same chain as above.
+  if constexpr (sizeof(Real) == 8) {
+    // binary64: one lane per site forms the site terms (planes of NT), then
+    // four lanes per site combine them with the target terms, two
+    // candidates each, so that the costly exponentials run in short
+    // independent chains.
+    Real *sTs = sT, *sGs = sT + NA * Sh::NT;
+    for (int t = tid; t < Sh::NT; t += kSweepThreads) {
+      const int cx = t % TX;
+      const int row = t / TX;
+      const int cy = row % TY;
+      const int bz = row / TY;
+      const int cz = bz % TZ;
+      const int b = bz / TZ;
+      const int sp = socc[oidx(b, cx, cy, cz)] >> 2;
+      const int ip = b * HV + ((cz + b) * HY + (cy + b)) * HX + (cx + b);
+      const uint2 cn = sCnt[ip];
+      Real g[NA];
+#pragma unroll
+      for (int A = 0; A < NA; ++A) g[A] = Real(0);
+#pragma unroll
+      for (int s = 1; s < S; ++s) {
+        const Real n1 = (Real)nib(cn.x, s), n2 = (Real)nib(cn.y, s);
+#pragma unroll
+        for (int A = 0; A < NA; ++A) g[A] = fma(n2, sDs2[A * S + s], fma(n1, sDs1[A * S + s], g[A]));
+      }
+#pragma unroll
+      for (int A = 0; A < NA; ++A) {
+        sTs[A * Sh::NT + t] = SW::site(sC[A * S + sp], h, g[A]);
+        if (WITH_EA) sGs[A * Sh::NT + t] = g[A];
+      }
+    }
+    __syncthreads();
+    constexpr int LPS = 8 / VW;
+    for (int it = tid; it < Sh::NT * LPS; it += kSweepThreads) {
+      const int t = it / LPS, part = it % LPS;
+      const int cx = t % TX;
+      const int row = t / TX;
+      const int cy = row % TY;
+      const int bz = row / TY;
+      const int cz = bz % TZ;
+      const int b = bz / TZ;
+      const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+      if (gx >= lx || gy >= ly || gz >= lz) continue;
+      const int sp = socc[oidx(b, cx, cy, cz)] >> 2;
+      const int ij0 = (1 - b) * HV + (cz * HY + cy) * HX + cx;
+      const uint8_t *s1 = socc + oidx(1 - b, cx - 1 + b, cy - 1 + b, cz - 1 + b);
+      vecw w, we;
+#pragma unroll
+      for (int c = 0; c < VW; ++c) {
+        const int k = part * VW + c;
+        const int px = (k >> 2) & 1, py = (k >> 1) & 1, pz = k & 1;
+        const int A = s1[px + py * EX + pz * (EX * EY)] >> 2;
+        const int Ac = min(A, NA - 1);
+        const int ij = ij0 + (pz * HY + py) * HX + px;
+        const Real ts = A == V ? SW::masked_site() : sTs[Ac * Sh::NT + t];
+        w[c] = SW::rate(ts, sE[ij]);
+        if (WITH_EA)
+          we[c] = A == V ? inf_of<Real>()
+                         : se0[Ac] + Real(0.5) * ((sGs[Ac * Sh::NT + t] - sH[ij]) + sK[Ac * S + sp]);
+      }
+      const size_t site = (unsigned)(b * ncell + (gz * ly + gy) * lx + gx);
+      __builtin_nontemporal_store(w, (vecw *)(rates + site * 8) + part);
+      if (WITH_EA) __builtin_nontemporal_store(we, (vecw *)(ea + site * 8) + part);
+    }
+    return;
+  }
+  // binary32: one lane per site; the grid-uniform tables sit in scalar
+  // registers and the site terms in a per-lane LDS table.
+  const Real *Ds1 = Tab<Real>::Ds1(d), *Ds2 = Tab<Real>::Ds2(d);
+  Real *myT = sT + tid;
+  myT[NA * kSweepThreads] = SW::masked_site();  // code of the vacancy
+  for (int t = tid; t < Sh::NT; t += kSweepThreads) {
+    const int cx = t % TX;
+    const int row = t / TX;
     const int cy = row % TY;
     const int bz = row / TY;
     const int cz = bz % TZ;
     const int b = bz / TZ;
     const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
     if (gx >= lx || gy >= ly || gz >= lz) continue;
-    const int sp4 = socc[oidx(b, cx, cy, cz)];
-    // Field planes are species-major (plane A holds G'_A of every region
-    // site), so neighbouring lanes read neighbouring words.
+    const int sp = socc[oidx(b, cx, cy, cz)] >> 2;
     const int ip = b * HV + ((cz + b) * HY + (cy + b)) * HX + (cx + b);
     const int ij0 = (1 - b) * HV + (cz * HY + cy) * HX + cx;
     const uint8_t *s1 = socc + oidx(1 - b, cx - 1 + b, cy - 1 + b, cz - 1 + b);
-    int a4[VW];
+    const uint2 cn = sCnt[ip];
+    Real g[NA];
 #pragma unroll
-    for (int c = 0; c < VW; ++c) {
-      const int k = part * VW + c;
-      a4[c] = s1[((k >> 2) & 1) + ((k >> 1) & 1) * EX + (k & 1) * (EX * EY)];
-    }
-    // Byte offsets: a brick code is 4*species, so plane A of the field
-    // starts at code * (2*HV) words and table entry [A][s] at code*S + 4*s
-    // bytes (binary32; twice that for binary64).
-    constexpr int WS = (int)sizeof(Real) / 4;
-    const unsigned char *gb = reinterpret_cast<const unsigned char *>(sG);
-    Real gpa[VW], gja[VW], cc[VW], e0a[VW], kk[VW];
+    for (int A = 0; A < NA; ++A) g[A] = Real(0);
 #pragma unroll
-    for (int c = 0; c < VW; ++c) {
-      const int k = part * VW + c;
-      const int px = (k >> 2) & 1, py = (k >> 1) & 1, pz = k & 1;
-      const int a4c = min(a4[c], 4 * (NA - 1));
-      const int plane = a4c * (2 * HV * WS);
-      gpa[c] = *reinterpret_cast<const Real *>(gb + plane + ip * (int)sizeof(Real));
-      gja[c] = *reinterpret_cast<const Real *>(gb + plane + (ij0 + (pz * HY + py) * HX + px) * (int)sizeof(Real));
-      const int tab = (a4c * S + sp4) * WS;
-      cc[c] = *reinterpret_cast<const Real *>(reinterpret_cast<const unsigned char *>(sC) + tab);
-      if (WITH_EA) {
-        e0a[c] = *reinterpret_cast<const Real *>(reinterpret_cast<const unsigned char *>(se0) + a4c * WS);
-        kk[c] = *reinterpret_cast<const Real *>(reinterpret_cast<const unsigned char *>(sK) + tab);
-      }
-    }
-    vecw rr, ee;
+    for (int s = 1; s < S; ++s) {
+      const Real n1 = (Real)nib(cn.x, s), n2 = (Real)nib(cn.y, s);
 #pragma unroll
-    for (int c = 0; c < VW; ++c) {
-      const bool masked = a4[c] == 4 * V;
-      const Real r = Sweep<Real>::rate(cc[c], h, gja[c] - gpa[c]);
-      rr[c] = masked ? Real(0) : r;
-      if (WITH_EA) ee[c] = masked ? inf_of<Real>() : e0a[c] + Real(0.5) * ((gpa[c] - gja[c]) + kk[c]);
+      for (int A = 0; A < NA; ++A) g[A] = fma(n2, Ds2[A * S + s], fma(n1, Ds1[A * S + s], g[A]));
     }
+#pragma unroll
+    for (int A = 0; A < NA; ++A) myT[A * kSweepThreads] = SW::site(sC[A * S + sp], h, g[A]);
     // Site indices stay below 2^31 (checked at create).
     const size_t site = (unsigned)(b * ncell + (gz * ly + gy) * lx + gx);
-    __builtin_nontemporal_store(rr, (vecw *)(rates + site * 8) + part);
-    if (WITH_EA) __builtin_nontemporal_store(ee, (vecw *)(ea + site * 8) + part);
+    vecw *out = (vecw *)(rates + site * 8);
+    vecw *oe = WITH_EA ? (vecw *)(ea + site * 8) : nullptr;
+    constexpr int NVEC = 8 / VW;
+#pragma unroll
+    for (int v = 0; v < NVEC; ++v) {
+      vecw w, we;
+#pragma unroll
+      for (int c = 0; c < VW; ++c) {
+        const int k = v * VW + c;
+        const int px = (k >> 2) & 1, py = (k >> 1) & 1, pz = k & 1;
+        const int A = s1[px + py * EX + pz * (EX * EY)] >> 2;
+        const int ij = ij0 + (pz * HY + py) * HX + px;
+        w[c] = SW::rate(myT[A * kSweepThreads], sE[ij]);
+        if (WITH_EA) {
+          Real ga = g[0];
+#pragma unroll
+          for (int m = 1; m < NA; ++m) ga = A == m ? g[m] : ga;
+          const int Ac = min(A, NA - 1);
+          we[c] = A == V ? inf_of<Real>() : se0[Ac] + Real(0.5) * ((ga - sH[ij]) + sK[Ac * S + sp]);
+        }
+      }
+      __builtin_nontemporal_store(w, out + v);
+      if (WITH_EA) __builtin_nontemporal_store(we, oe + v);
+    }
   }
 }
 
@@ -359,7 +449,7 @@ static hipError_t launch_sweep(const LatDesc *d_desc, const LatDesc &h, const ui
   using Sh = SweepShape<TX, TY, TZ>;
   const unsigned tiles = (unsigned)(((h.lx + TX - 1) / TX) * ((h.ly + TY - 1) / TY) *
                                     ((h.lz + TZ - 1) / TZ));
-  const size_t lds = Sh::lds_bytes(S, sizeof(Real));
+  const size_t lds = Sh::lds_bytes(S, sizeof(Real), ea != nullptr);
   auto k = ea ? k_rates_all<TX, TY, TZ, S, Real, true> : k_rates_all<TX, TY, TZ, S, Real, false>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -373,11 +463,9 @@ static hipError_t launch_sweep(const LatDesc *d_desc, const LatDesc &h, const ui
 template <int S, class Real>
 static hipError_t launch_sweep_s(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                                  void *rates, void *ea, hipStream_t stream) {
-  // The field holds S-1 values per region site: binary64 and many species
-  // take the narrower brick so that several workgroups share a CU.
-  if (sizeof(Real) == 4 && S <= 5)
-    return launch_sweep<32, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
-  return launch_sweep<16, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
+  // binary64 takes the narrower brick so that several workgroups share a CU
+  if (sizeof(Real) == 8) return launch_sweep<16, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
+  return launch_sweep<32, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
 }
 
 template <class Real>
