@@ -89,7 +89,9 @@ def test_all_sites_full_size_sampled(oracle_mod, precision):
     spec = W.rpv_4m()
     lat = akmc.Lattice(spec, precision=precision)
     r, e = lat.rates(akmc.RATES_ALL_SITES, with_ea=True)
+    r_only = lat.rates(akmc.RATES_ALL_SITES)          # the launch the benchmark times
     torch.cuda.synchronize()
+    assert torch.equal(r, r_only)
     rng = np.random.default_rng(11)
     L = 128
     edge = [((b * L + z) * L + y) * L + x for b in (0, 1) for z in (0, L - 1) for y in (0, 31, 32, L - 1)
@@ -118,3 +120,19 @@ def test_rates_eval_bad_mode_is_an_error():
     with pytest.raises(akmc.AkmcError):
         akmc.rates_eval(lat.h, akmc.RATES_SITES, None, 5, out)
     lat.close()
+
+
+@pytest.mark.parametrize("precision", [akmc.FP64, akmc.FP32])
+@pytest.mark.parametrize("dims,S,nv,seed", CASES)
+def test_all_sites_rates_only_equal_rates_with_barriers(dims, S, nv, seed, precision):
+    """The sweep without the barrier output computes the same rates, bit for
+    bit, as the one with it (whose rates are compared with the oracle)."""
+    import torch
+    banner("all sites rates-only dims=%s S=%d precision=%d" % (dims, S, precision))
+    spec = W.random_lattice(np.random.default_rng(seed), dims, S, nv, solute_total=0.3)
+    lat = akmc.Lattice(spec, precision=precision)
+    r, _ = lat.rates(akmc.RATES_ALL_SITES, with_ea=True)
+    r_only = lat.rates(akmc.RATES_ALL_SITES)
+    torch.cuda.synchronize()
+    lat.close()
+    assert torch.equal(r, r_only)
