@@ -83,16 +83,22 @@ __device__ __forceinline__ float bf2f(unsigned short h) {
   return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
 
-__device__ __forceinline__ float gelu_f(float z) {
-  const float c = 0.7978845608028654f;  // sqrt(2/pi)
-  const float u = c * (z + 0.044715f * z * z * z);
-  return 0.5f * z * (1.0f + tanhf(u));
+// GELU in its tanh form, evaluated as z times a logistic function:
+//   gelu(z) = z/2 (1 + tanh u) = z s,  s = 1 / (1 + e^{-2u}),
+//   u = sqrt(2/pi) (z + 0.044715 z^3),
+// with one hardware base-2 exponential and one reciprocal (about 1e-7
+// relative, far below the bfloat16 rounding of the activations).
+__device__ __forceinline__ float gelu_sig(float z) {
+  const float k = 2.0f * 0.7978845608028654f * 1.4426950408889634f;  // 2 sqrt(2/pi) log2(e)
+  const float t = z * fmaf(0.044715f * z, z, 1.0f);
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-k * t));
 }
+__device__ __forceinline__ float gelu_f(float z) { return z * gelu_sig(z); }
+// d/dz [z s] = s + z s (1 - s) 2u'(z),  u' = sqrt(2/pi) (1 + 3 * 0.044715 z^2)
 __device__ __forceinline__ float gelu_grad_f(float z) {
   const float c = 0.7978845608028654f;
-  const float u = c * (z + 0.044715f * z * z * z);
-  const float t = tanhf(u);
-  return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * z * z);
+  const float s = gelu_sig(z);
+  return s + z * s * (1.0f - s) * (2.0f * c) * fmaf(3.0f * 0.044715f * z, z, 1.0f);
 }
 
 // Forward pass of 16 rows by one wavefront.
