@@ -6,18 +6,17 @@
 //    the loop's rates bit for bit.
 //
 //  k_rates_all: the bulk sweep over every lattice site (a vacancy placed
-//    at each site in turn).  It is bound by the HBM write of the
-//    [N][8] rate array.  A workgroup stages a brick of occupancy with a
-//    halo of 2 cells (4 along x, for dword-aligned rows) in LDS, computes for every site q that can be a jump
-//    target the field H(q) = sum over its 14 bonds of
-//        D'_k[s_q][s_n] = D_k[s_q][s_n] - D_k[s_q][Fe],
-//    and for every site p of the brick the same field G'_A(p) for each
-//    mover species A.  Because the pair energy is a sum over bonds, the
-//    energy change of the jump p <- j (species A = s_j) is
-//        dE = G'_A(p) - H(j) + D1[A][s_p] - D1[A][A],
+//    at each site in turn), nominally bound by the HBM write of the [N][8]
+//    rate array.  A workgroup stages a brick of occupancy with a halo of
+//    2 cells (4 along x, for dword-aligned rows) in LDS.  With the field
+//        G'_A(q) = sum over the 14 bonds of q of D'_k[A][s_n],
+//        D'_k[A][s] = D_k[A][s] - D_k[A][Fe],
+//    the energy change of the jump p <- j (species A = s_j) is
+//        dE = G'_A(p) - G'_A(j) + D1[A][s_p] - D1[A][A],
 //    which equals the bond-count form up to rounding; measuring the field
-//    against the all-Fe environment keeps it near zero, so binary32
-//    keeps its relative accuracy.
+//    against the all-Fe environment keeps it near zero, so binary32 keeps
+//    its relative accuracy.  A target enters with its own species only.
+
 #include <hip/hip_runtime.h>
 
 #include "akmc_device.hpp"
