@@ -76,7 +76,7 @@ template <int G>
 struct Group {
   int gw, gl, base;
   __device__ __forceinline__ uint64_t ballot(bool p) const {
-    const uint64_t m = __ballot(p);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(p);
     if (G == 64) return m;
     return (m >> base) & ((1ull << (G & 63)) - 1ull);
   }
@@ -593,12 +593,15 @@ struct Runner {
           const int cntA = min(8, nl(l) - base);
           const bool inA = c < cntA;
           const double *qa_p = Q(l) + base;
-          const double qa = inA ? qa_p[c] : 0.0;
-          const double qp = (inA && c > 0) ? qa_p[c - 1] : 0.0;
+          // Every lane reads a valid entry (indices clamped into range), so
+          // no read is predicated; out-of-range lanes are masked below.
+          const double qa = qa_p[min(c, cntA - 1)];
+          const double qp = qa_p[max(min(c, cntA - 1) - 1, 0)];
           const int baseB = 8 * (base + c);
           const int nlB = l >= 2 ? nl(l - 1) : 8 * nv;
           const bool inB = inA && c2 < min(8, nlB - baseB);
-          const double qb = inB ? (l >= 2 ? Q(l - 1)[baseB + c2] : s.part[baseB + c2]) : 0.0;
+          const int ib = min(baseB + c2, nlB - 1);
+          const double qb = l >= 2 ? Q(l - 1)[ib] : s.part[ib];
           const uint64_t mA = gp.ballot(c2 == 0 && inA && qa > tgt);
           if (mA) {
             const int cs = (__ffsll((unsigned long long)mA) - 1) >> 3;
