@@ -707,17 +707,16 @@ struct Runner {
         auto hits = [&](int b0, bool (&hit)[4]) {
           int qp[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int vv = b0 + u * G + gl;
-            qp[u] = vv < nv ? s.pos[vv] : -1;
-          }
+          for (int u = 0; u < 4; ++u) qp[u] = s.pos[min(b0 + u * G + gl, nv - 1)];  // unpredicated
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            int dx = abs(pos_x(qp[u]) - X), dy = abs(pos_y(qp[u]) - Y), dz = abs(pos_z(qp[u]) - Z);
+            // |d| by sum-of-absolute-differences, then the periodic image
+            int dx = (int)__sad(pos_x(qp[u]), X, 0u), dy = (int)__sad(pos_y(qp[u]), Y, 0u),
+                dz = (int)__sad(pos_z(qp[u]), Z, 0u);
             dx = min(dx, g.X2 - dx);
             dy = min(dy, g.Y2 - dy);
             dz = min(dz, g.Z2 - dz);
-            hit[u] = qp[u] >= 0 && max(dx, max(dy, dz)) <= 4;
+            hit[u] = b0 + u * G + gl < nv && max(dx, max(dy, dz)) <= 4;
           }
         };
         bool others = false;
