@@ -135,7 +135,7 @@ template <> struct Sweep<float> {
   __device__ static float rate(float t, float e) { return __builtin_amdgcn_exp2f(t + e); }
 };
 
-constexpr int kSweepThreads = 256;
+constexpr int kSweepThreads = 512;
 
 template <int TX, int TY, int TZ>
 struct SweepShape {
