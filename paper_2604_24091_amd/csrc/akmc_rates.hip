@@ -268,9 +268,12 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
 
   // Phase 2: for every region site q the bond counts (kept for the vacancy
   // role) and the target term from the field of q's own species.
-  for (int r = tid; r < 2 * HV; r += kSweepThreads) {
-    const int hx = r % HX;
-    const int row = r / HX;
+  // Threads sit on fixed columns hx of the region's rows (HX sites each);
+  // a pass covers RPP whole rows.
+  constexpr int RPP = kSweepThreads / HX;
+  const int hx = tid % HX, row0 = tid / HX;
+  for (int row = row0; row0 < RPP && row < 2 * HY * Sh::HZ; row += RPP) {
+    const int r = row * HX + hx;
     const int hy = row % HY;
     const int bz = row / HY;
     const int hz = bz % Sh::HZ;
