@@ -139,9 +139,10 @@ constexpr int kSweepThreads = 512;
 
 template <int TX, int TY, int TZ>
 struct SweepShape {
-  // Occupancy brick: cells [-2, T+2) in y and z and [-4, T+4) in x, so that
-  // every row starts on a 4-byte boundary and can be staged in dwords.
-  static constexpr int PX = 4;
+  // Occupancy brick: cells [-2, T+2) in y and z and [-8, T+8) in x, so that
+  // every row starts on an 8-byte boundary and can be staged in 8-byte
+  // vectors (TX a multiple of 8).
+  static constexpr int PX = 8;
   static constexpr int EX = TX + 2 * PX, EY = TY + 4, EZ = TZ + 4, EV = EX * EY * EZ;
   static constexpr int ROWS = 2 * EY * EZ;
   static constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, HV = HX * HY * HZ;  // field region
@@ -219,8 +220,29 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
   // when every edge exceeds the brick (then x is staged in aligned dwords if
   // lx is a multiple of 4); small lattices take the general modulo byte by
   // byte.
-  const bool simple = lx > TX + 2 && ly > TY + 2 && lz > TZ + 2;
-  if (simple && (lx & 3) == 0) {
+  // x spans [x0 - PX, x0 + TX + PX) with x0 <= lx - 1: one wrap suffices
+  // when lx >= TX + PX; y and z span 2 cells either side.
+  const bool simple = lx >= TX + PX && ly > TY + 2 && lz > TZ + 2;
+  static_assert(TX % 8 == 0 && PX % 8 == 0, "brick rows must start on 8-byte boundaries");
+  if (simple && (lx & 7) == 0) {
+    // EX / 8 vectors per row; with lx a multiple of 8 a vector never
+    // straddles the periodic seam.
+    constexpr int QW = EX / 8;
+    for (int i = tid; i < Sh::ROWS * QW; i += kSweepThreads) {
+      const int row = i / QW, w = i % QW;
+      const int ey = row % EY;
+      const int bz = row / EY;
+      const int ez = bz % EZ;
+      const int b = bz / EZ;
+      int gx = x0 - PX + 8 * w, gy = y0 + ey - 2, gz = z0 + ez - 2;
+      gx += gx < 0 ? lx : 0;  gx -= gx >= lx ? lx : 0;
+      gy += gy < 0 ? ly : 0;  gy -= gy >= ly ? ly : 0;
+      gz += gz < 0 ? lz : 0;  gz -= gz >= lz ? lz : 0;
+      uint2 v = *(const uint2 *)(occ + (size_t)b * ncell + (gz * ly + gy) * lx + gx);
+      v.x <<= 2; v.y <<= 2;  // codes < 8: no carry between bytes
+      *(uint2 *)(socc + row * EX + 8 * w) = v;
+    }
+  } else if (simple && (lx & 3) == 0) {
     // 16 lanes per brick row (DW <= 16 dwords used), rows in pow-2 strides.
     constexpr int DW = EX / 4;
     static_assert(DW <= 16, "brick row wider than 16 dwords");

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [((3, 3, 3), 3, 4, 1), ((5, 4, 6), 5, 12, 2), ((12, 12, 12), 5, 40, 3),
          ((37, 5, 9), 5, 30, 4), ((33, 34, 35), 4, 100, 5), ((20, 7, 11), 8, 50, 6),
-         ((40, 9, 6), 2, 20, 7)]
+         ((40, 9, 6), 2, 20, 7), ((44, 7, 7), 5, 20, 8), ((41, 7, 6), 3, 10, 9)]
 
 
 def _compare(spec, oracle_mod, precision, mode):
