@@ -103,11 +103,9 @@ LatDesc make_desc(const akmc_params *p, int nv) {
     }
   for (int A = 0; A < S; ++A)
     for (int s = 0; s < S; ++s) {
-      const double s1 = d.D1[A * 8 + s] - d.D1[A * 8 + 0];
-      const double s2 = d.D2[A * 8 + s] - d.D2[A * 8 + 0];
       const double kk = d.D1[A * 8 + s] - d.D1[A * 8 + A];
-      d.Ds1[A * S + s] = s1; d.Ds2[A * S + s] = s2; d.K[A * S + s] = kk;
-      d.Ds1f[A * S + s] = (float)s1; d.Ds2f[A * S + s] = (float)s2; d.Kf[A * S + s] = (float)kk;
+      d.K[A * S + s] = kk;
+      d.Kf[A * S + s] = (float)kk;
     }
   for (int a = 0; a < S - 1; ++a) {
     d.e0[a] = p->e0[a];
@@ -130,6 +128,30 @@ LatDesc make_desc(const akmc_params *p, int nv) {
       d.C2f[A * S + s] = (float)(c * log2e);
     }
   d.h2f = (float)(d.half_beta * log2e);
+  d.inv_half_beta = 1.0 / d.half_beta;
+  d.inv_h2f = 1.0f / d.h2f;
+  for (int A = 0; A < S; ++A)
+    for (int s = 0; s < S; ++s) {
+      const double s1 = d.D1[A * 8 + s] - d.D1[A * 8 + 0];
+      const double s2 = d.D2[A * 8 + s] - d.D2[A * 8 + 0];
+      d.Hs1[A * 8 + s] = d.half_beta * s1;
+      d.Hs2[A * 8 + s] = d.half_beta * s2;
+      d.Hs1f[A * 8 + s] = (float)(d.half_beta * log2e * s1);
+      d.Hs2f[A * 8 + s] = (float)(d.half_beta * log2e * s2);
+    }
+  // |hG_A| <= 8 max_s |Hs1[A][s]| + 6 max_s |Hs2[A][s]| (8 first and 6
+  // second neighbours); the site exponent adds at most max |Cn|.
+  double field = 0.0, cmax = 0.0;
+  for (int A = 0; A < S; ++A) {
+    double m1 = 0.0, m2 = 0.0;
+    for (int s = 0; s < S; ++s) {
+      m1 = std::max(m1, std::fabs(d.Hs1[A * 8 + s]));
+      m2 = std::max(m2, std::fabs(d.Hs2[A * 8 + s]));
+      cmax = std::max(cmax, std::fabs(d.Cn[A * S + s]));
+    }
+    field = std::max(field, 8.0 * m1 + 6.0 * m2);
+  }
+  d.sweep_factor_ok = cmax + field <= 700.0 ? 1 : 0;
   return d;
 }
 

@@ -26,10 +26,14 @@ struct LatDesc {
   float D1f[64], D2f[64];
   float e0f[8];
   float nuf, kTf;
-  // Tables of the bulk sweep (relative to the all-Fe environment):
-  //   Ds_k[A][s] = D_k[A][s] - D_k[A][0],  K[A][s] = D1[A][s] - D1[A][A].
-  double Ds1[64], Ds2[64], K[64];
-  float Ds1f[64], Ds2f[64], Kf[64];
+  // Tables of the bulk sweep (relative to the all-Fe environment), scaled by
+  // the exponent's factor h (beta/2 in binary64, (beta/2) log2(e) in
+  // binary32), rows of 8 at 8*A for every code A (zero for s >= S):
+  //   Hs_k[A][s] = h (D_k[A][s] - D_k[A][0]);  K[A][s] = D1[A][s] - D1[A][A].
+  double Hs1[64], Hs2[64], K[64];
+  alignas(64) float Hs1f[64];
+  alignas(64) float Hs2f[64];
+  float Kf[64];
   double beta;                // 1/kT
   float betaf;
   int32_t pad_[1];
@@ -37,10 +41,13 @@ struct LatDesc {
   // with Cn[A][s] = ln(nu) - beta*e0[A] - (beta/2)*K[A][s];  C2f is Cn*log2(e)
   // in binary32 and h2f = (beta/2)*log2(e), for a base-2 exponential.
   double Cn[64];
-  double half_beta;
+  double half_beta, inv_half_beta;
   float C2f[64];
-  float h2f;
-  int32_t pad2_[1];
+  float h2f, inv_h2f;
+  // binary64 sweep: every factor exp(Cn - hG) and exp(hG) is bounded by
+  // exp(700) either way for these tables (else the sweep is not used)
+  int32_t sweep_factor_ok;
+  int32_t pad2_;
 };
 
 // Mutable per-lattice state.

@@ -8,7 +8,7 @@
 //  k_rates_all: the bulk sweep over every lattice site (a vacancy placed
 //    at each site in turn), nominally bound by the HBM write of the [N][8]
 //    rate array.  A workgroup stages a brick of occupancy with a halo of
-//    2 cells (4 along x, for dword-aligned rows) in LDS.  With the field
+//    2 cells (8 along x, for 8-byte aligned rows) in LDS.  With the field
 //        G'_A(q) = sum over the 14 bonds of q of D'_k[A][s_n],
 //        D'_k[A][s] = D_k[A][s] - D_k[A][Fe],
 //    the energy change of the jump p <- j (species A = s_j) is
@@ -29,8 +29,8 @@ template <> struct Tab<double> {
   __device__ static const double *D1(const LatDesc *d) { return d->D1; }
   __device__ static const double *D2(const LatDesc *d) { return d->D2; }
   __device__ static const double *e0(const LatDesc *d) { return d->e0; }
-  __device__ static const double *Ds1(const LatDesc *d) { return d->Ds1; }
-  __device__ static const double *Ds2(const LatDesc *d) { return d->Ds2; }
+  __device__ static const double *Hs1(const LatDesc *d) { return d->Hs1; }
+  __device__ static const double *Hs2(const LatDesc *d) { return d->Hs2; }
   __device__ static const double *K(const LatDesc *d) { return d->K; }
   __device__ static double nu(const LatDesc *d) { return d->nu; }
   __device__ static double kT(const LatDesc *d) { return d->kT; }
@@ -40,8 +40,8 @@ template <> struct Tab<float> {
   __device__ static const float *D1(const LatDesc *d) { return d->D1f; }
   __device__ static const float *D2(const LatDesc *d) { return d->D2f; }
   __device__ static const float *e0(const LatDesc *d) { return d->e0f; }
-  __device__ static const float *Ds1(const LatDesc *d) { return d->Ds1f; }
-  __device__ static const float *Ds2(const LatDesc *d) { return d->Ds2f; }
+  __device__ static const float *Hs1(const LatDesc *d) { return d->Hs1f; }
+  __device__ static const float *Hs2(const LatDesc *d) { return d->Hs2f; }
   __device__ static const float *K(const LatDesc *d) { return d->Kf; }
   __device__ static float nu(const LatDesc *d) { return d->nuf; }
   __device__ static float kT(const LatDesc *d) { return d->kTf; }
@@ -114,26 +114,39 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
 // ---------------------------------------------------------- bulk sweep
 
 template <class Real> struct Sweep;
-// The rate of candidate p <- j as one exponential of the sum of a per-site
-// term and a per-target term (see k_rates_all):
-//   binary64:  ln r    = (Cn[A][s_p]  - h G'_A(p)) + h G'_{s_j}(j),  h = beta/2
-//   binary32:  log2 r  = (C2f[A][s_p] - h G'_A(p)) + h G'_{s_j}(j),  h = (beta/2) log2(e)
+// The rate of candidate p <- j from a per-site term and a per-target term
+// (see k_rates_all), with the field accumulated from tables already scaled
+// by h (hG = h G'):
+//   binary64:  r = exp(Cn[A][s_p] - hG_A(p)) * exp(hG_{s_j}(j)),   h = beta/2
+//   binary32:  r = 2^((C2f[A][s_p] - hG_A(p)) + hG_{s_j}(j)),      h = (beta/2) log2(e)
+// binary64 takes the product of two factors, so that a site costs S-1
+// exponentials for its movers plus one for its own target role instead of
+// one per candidate (its costly exponential dominates); each factor must
+// stay inside binary64's exponent range, which the host checks from the
+// tables before it picks this kernel.  binary32's range is too narrow for
+// the factors, and its hardware exponential is cheap: one per candidate.
+// The barrier, when asked for, is e0[A] + (G'_A(p) - G'_A(j) + K[A][s_p]) / 2
+// with G' = hG / h.
 template <> struct Sweep<double> {
-  __device__ static double h(const LatDesc *d) { return d->half_beta; }
+  static constexpr bool kFactor = true;
+  __device__ static double inv_h(const LatDesc *d) { return d->inv_half_beta; }
   __device__ static double table(const LatDesc *d, int i) { return d->Cn[i]; }
-  __device__ static double target(double h, double H) { return h * H; }
-  __device__ static double site(double c, double h, double g) { return c - h * g; }
-  __device__ static double masked_site() { return -__builtin_huge_val(); }
-  __device__ static double rate(double t, double e) { return exp(t + e); }
+  __device__ static double ex(double t) { return exp(t); }
 };
 template <> struct Sweep<float> {
-  __device__ static float h(const LatDesc *d) { return d->h2f; }
+  static constexpr bool kFactor = false;
+  __device__ static float inv_h(const LatDesc *d) { return d->inv_h2f; }
   __device__ static float table(const LatDesc *d, int i) { return d->C2f[i]; }
-  __device__ static float target(float h, float H) { return h * H; }
-  __device__ static float site(float c, float h, float g) { return c - h * g; }
-  __device__ static float masked_site() { return -__builtin_huge_valf(); }
-  __device__ static float rate(float t, float e) { return __builtin_amdgcn_exp2f(t + e); }
+  __device__ static float ex(float t) { return __builtin_amdgcn_exp2f(t); }
 };
+
+// Species count s of a packed nibble count vector c, as a real, from the
+// even (c & 0x0f0f0f0f) or odd ((c >> 4) & 0x0f0f0f0f) nibbles: one byte
+// conversion per count.
+template <class Real>
+__device__ __forceinline__ Real count_of(uint32_t ev, uint32_t od, int s) {
+  return (Real)(((s & 1) ? od : ev) >> (8 * (s >> 1)) & 0xffu);
+}
 
 constexpr int kSweepThreads = 512;
 
@@ -148,14 +161,15 @@ struct SweepShape {
   static constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, HV = HX * HY * HZ;  // field region
   static constexpr int NT = 2 * TX * TY * TZ;                                     // brick sites
   static constexpr int OCC_BYTES = (2 * EV + 15) & ~15;
-  // per region site: bond counts (2 words), the target term, the field
-  // (barrier output only); site terms: binary32 per lane (S planes of 256),
-  // binary64 per brick site (S-1 planes of NT, twice with the barrier output)
+  // per region site: bond counts (2 words), the target factor and (barrier
+  // output only) its field; site factors: binary32 per lane (S planes of
+  // kSweepThreads), binary64 per brick site (S-1 planes of NT, twice with
+  // the barrier output)
   __host__ __device__ static constexpr size_t terms(int S, size_t real, bool with_ea) {
     return real == 4 ? (size_t)S * kSweepThreads : (size_t)(S - 1) * NT * (with_ea ? 2 : 1);
   }
   static size_t lds_bytes(int S, size_t real, bool with_ea) {
-    return OCC_BYTES + (size_t)2 * HV * (8 + real + (with_ea ? real : 0)) +
+    return OCC_BYTES + (size_t)2 * HV * (8 + real + (with_ea && real == 8 ? real : 0)) +
            terms(S, real, with_ea) * real;
   }
 };
@@ -166,14 +180,15 @@ struct SweepShape {
 // a centre the corners at c + [s > 0]; both sit at index h = c + [s > 0] of
 // the other sublattice.
 //
-// With the field G'_A(q) = sum_s n1_s(q) Ds1[A][s] + n2_s(q) Ds2[A][s], the
-// rate of p <- j (species A = s_j) is, in logarithms,
-//   ln r = Cn[A][s_p] - h G'_A(p) + h G'_A(j),
+// With the field G'_A(q) = sum_s n1_s(q) Ds1[A][s] + n2_s(q) Ds2[A][s]
+// (accumulated as hG = h G' from the scaled tables Hs = h Ds), the rate of
+// p <- j (species A = s_j) is, in logarithms,
+//   ln r = Cn[A][s_p] - hG_A(p) + hG_A(j),
 // and a target enters only with its own species (A = s_j).  Phase 2 stores
-// per region site its counts and its target term; phase 3 forms per brick
-// site the term of every mover species (a per-lane table in LDS, whose
-// entry for the vacancy code gives a zero rate) and combines it with the
-// target terms of the 8 neighbours.
+// per region site its counts and its target term hG(q) (binary64: the
+// factor exp(hG(q))); phase 3 forms per brick site the term of every mover
+// species (a table in LDS whose entry for the vacancy code gives a zero
+// rate) and combines it with the target terms of the 8 neighbours.
 //
 // Output: one lane per site writes its 8 rates as two (binary32) or four
 // (binary64) 16-byte non-temporal vectors; neighbouring lanes write
@@ -186,28 +201,40 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
   using Sh = SweepShape<TX, TY, TZ>;
   using SW = Sweep<Real>;
   constexpr int EX = Sh::EX, EY = Sh::EY, EZ = Sh::EZ, EV = Sh::EV, PX = Sh::PX;
-  constexpr int HX = Sh::HX, HY = Sh::HY, HV = Sh::HV;
+  constexpr int HX = Sh::HX, HY = Sh::HY, HZ = Sh::HZ, HV = Sh::HV;
   constexpr int V = S - 1, NA = S - 1;
   constexpr int VW = 16 / (int)sizeof(Real);  // candidates per 16-byte store
   typedef Real vecw __attribute__((ext_vector_type(VW)));
   extern __shared__ __align__(16) unsigned char sweep_lds[];
   uint8_t *socc = sweep_lds;
   uint2 *sCnt = (uint2 *)(sweep_lds + Sh::OCC_BYTES);
-  Real *sE = (Real *)(sCnt + 2 * HV);
-  Real *sT = sE + 2 * HV;              // site terms
-  Real *sH = sT + Sh::terms(S, sizeof(Real), WITH_EA);  // WITH_EA only
-  __shared__ Real sC[64], sDs1[64], sDs2[64], se0[8], sK[64];
+  Real *sE = (Real *)(sCnt + 2 * HV);  // target terms (binary32) or factors (binary64)
+  Real *sT = sE + 2 * HV;              // site terms or factors
+  Real *sH = sT + Sh::terms(S, sizeof(Real), WITH_EA);  // binary64 barrier output: hG
+  __shared__ Real sC[64], sHs1[64], sHs2[64], se0[8], sK[64];
 
   const int tid = threadIdx.x;
   const int lx = d->lx, ly = d->ly, lz = d->lz;
   const int ncell = lx * ly * lz;
   if (tid < 64) {
     sC[tid] = SW::table(d, tid);
-    sDs1[tid] = Tab<Real>::Ds1(d)[tid];
-    sDs2[tid] = Tab<Real>::Ds2(d)[tid];
+    sHs1[tid] = Tab<Real>::Hs1(d)[tid];
+    sHs2[tid] = Tab<Real>::Hs2(d)[tid];
     if (WITH_EA) sK[tid] = Tab<Real>::K(d)[tid];
   }
   if (WITH_EA && tid < 8) se0[tid] = Tab<Real>::e0(d)[tid];
+
+  // binary32: the grid-uniform field tables, read at the start into scalar
+  // registers (rows of 8 at 8*A, the movers' rows only).
+  Real H1[NA * 8], H2[NA * 8];
+  if constexpr (sizeof(Real) == 4) {
+    const Real *Hs1 = Tab<Real>::Hs1(d), *Hs2 = Tab<Real>::Hs2(d);
+#pragma unroll
+    for (int i = 0; i < NA * 8; ++i) {
+      H1[i] = Hs1[i];
+      H2[i] = Hs2[i];
+    }
+  }
 
   const int ntx = (lx + TX - 1) / TX, nty = (ly + TY - 1) / TY;
   const int tile = blockIdx.x;
@@ -217,30 +244,32 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
 
   // Phase 1: occupancy brick of both sublattices, as 4*species (the shift of
   // that species' count nibble).  One conditional wrap per axis suffices
-  // when every edge exceeds the brick (then x is staged in aligned dwords if
-  // lx is a multiple of 4); small lattices take the general modulo byte by
-  // byte.
-  // x spans [x0 - PX, x0 + TX + PX) with x0 <= lx - 1: one wrap suffices
-  // when lx >= TX + PX; y and z span 2 cells either side.
+  // when every edge exceeds the brick: x spans [x0 - PX, x0 + TX + PX) with
+  // x0 <= lx - 1, so one wrap suffices when lx >= TX + PX; y and z span 2
+  // cells either side.  Small lattices take the general modulo byte by byte.
   const bool simple = lx >= TX + PX && ly > TY + 2 && lz > TZ + 2;
   static_assert(TX % 8 == 0 && PX % 8 == 0, "brick rows must start on 8-byte boundaries");
   if (simple && (lx & 7) == 0) {
-    // EX / 8 vectors per row; with lx a multiple of 8 a vector never
+    // Eight lanes per row (the first EX/8 load), one pass of the workgroup
+    // per sublattice: the indices are formed once and both sublattices'
+    // loads are in flight together.  With lx a multiple of 8 a vector never
     // straddles the periodic seam.
     constexpr int QW = EX / 8;
-    for (int i = tid; i < Sh::ROWS * QW; i += kSweepThreads) {
-      const int row = i / QW, w = i % QW;
-      const int ey = row % EY;
-      const int bz = row / EY;
-      const int ez = bz % EZ;
-      const int b = bz / EZ;
+    static_assert(QW <= 8 && EY * EZ * 8 == kSweepThreads, "one pass per sublattice");
+    const int w = tid & 7, ey = (tid >> 3) % EY, ez = (tid >> 3) / EY;
+    if (w < QW) {
       int gx = x0 - PX + 8 * w, gy = y0 + ey - 2, gz = z0 + ez - 2;
       gx += gx < 0 ? lx : 0;  gx -= gx >= lx ? lx : 0;
       gy += gy < 0 ? ly : 0;  gy -= gy >= ly ? ly : 0;
       gz += gz < 0 ? lz : 0;  gz -= gz >= lz ? lz : 0;
-      uint2 v = *(const uint2 *)(occ + (size_t)b * ncell + (gz * ly + gy) * lx + gx);
-      v.x <<= 2; v.y <<= 2;  // codes < 8: no carry between bytes
-      *(uint2 *)(socc + row * EX + 8 * w) = v;
+      const uint8_t *src = occ + (gz * ly + gy) * lx + gx;
+      uint2 v0 = *(const uint2 *)src;
+      uint2 v1 = *(const uint2 *)(src + ncell);
+      // codes < 8: no carry between bytes
+      v0.x <<= 2; v0.y <<= 2; v1.x <<= 2; v1.y <<= 2;
+      uint8_t *dst = socc + (ez * EY + ey) * EX + 8 * w;
+      *(uint2 *)dst = v0;
+      *(uint2 *)(dst + EV) = v1;
     }
   } else if (simple && (lx & 3) == 0) {
     // 16 lanes per brick row (DW <= 16 dwords used), rows in pow-2 strides.
@@ -286,39 +315,56 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
   auto oidx = [&](int b, int cx, int cy, int cz) {
     return b * EV + ((cz + 2) * EY + (cy + 2)) * EX + (cx + PX);
   };
-  const Real h = SW::h(d);
 
   // Phase 2: for every region site q the bond counts (kept for the vacancy
-  // role) and the target term from the field of q's own species.
-  // Threads sit on fixed columns hx of the region's rows (HX sites each);
-  // a pass covers RPP whole rows.
-  constexpr int RPP = kSweepThreads / HX;
-  const int hx = tid % HX, row0 = tid / HX;
-  for (int row = row0; row0 < RPP && row < 2 * HY * Sh::HZ; row += RPP) {
-    const int r = row * HX + hx;
-    const int hy = row % HY;
-    const int bz = row / HY;
-    const int hz = bz % Sh::HZ;
-    const int b = bz / Sh::HZ;
-    const int cx = hx - b, cy = hy - b, cz = hz - b;
-    // First shell: the other sublattice's cube of cells c-1..c (corner) or
-    // c..c+1 (centre); second shell: same sublattice, +-1 cell per axis.
-    const uint8_t *s1 = socc + oidx(1 - b, cx - 1 + b, cy - 1 + b, cz - 1 + b);
-    const uint8_t *s2 = socc + oidx(b, cx, cy, cz);
-    uint32_t c1 = 0;
+  // role) and the target factor from the field of q's own species.  A thread
+  // keeps one column hx and one row hy of the region and walks the z planes
+  // of each sublattice BZP at a time (the planes b*HZ + hz congruent to its
+  // first one modulo BZP), so that only the plane offset changes per step.
+  constexpr int RPP = kSweepThreads / HX;  // region rows per pass
+  constexpr int BZP = RPP / HY;            // planes per pass
+  static_assert(BZP >= 1, "region row count");
+  {
+    const int hx = tid % HX, r0 = tid / HX;
+    const int hy = r0 % HY, bz0 = r0 / HY;
+    if (bz0 < BZP) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) c1 += 1u << s1[((q >> 2) & 1) + ((q >> 1) & 1) * EX + (q & 1) * (EX * EY)];
-    const uint32_t c2 = (1u << s2[1]) + (1u << s2[-1]) + (1u << s2[EX]) + (1u << s2[-EX]) +
-                        (1u << s2[EX * EY]) + (1u << s2[-EX * EY]);
-    sCnt[r] = make_uint2(c1, c2);
-    // A vacancy is never a target: its entry is computed for a mover, unused.
-    const int A = min((int)s2[0] >> 2, NA - 1);
-    Real g = Real(0);
+      for (int b = 0; b < 2; ++b) {
+        // Region site (b, c = h - b): first shell on the other sublattice's
+        // cube of cells c-1..c (corner) or c..c+1 (centre), i.e. h-1..h;
+        // second shell on the same sublattice, +-1 cell per axis.
+        const uint8_t *s1b = socc + oidx(1 - b, hx - 1, hy - 1, -1);
+        const uint8_t *s2b = socc + oidx(b, hx - b, hy - b, -b);
+        const int rb = (b * HZ * HY + hy) * HX + hx;
+        const int hz0 = b == 0 ? bz0 : ((bz0 - HZ) % BZP + BZP) % BZP;
+        for (int hz = hz0; hz < HZ; hz += BZP) {
+          const int r = rb + hz * (HY * HX);
+          const uint8_t *s1 = s1b + hz * (EY * EX);
+          const uint8_t *s2 = s2b + hz * (EY * EX);
+          uint32_t c1 = 0;
 #pragma unroll
-    for (int s = 1; s < S; ++s)
-      g = fma((Real)nib(c2, s), sDs2[A * S + s], fma((Real)nib(c1, s), sDs1[A * S + s], g));
-    sE[r] = SW::target(h, g);
-    if (WITH_EA) sH[r] = g;
+          for (int q = 0; q < 8; ++q) c1 += 1u << s1[((q >> 2) & 1) + ((q >> 1) & 1) * EX + (q & 1) * (EX * EY)];
+          const uint32_t c2 = (1u << s2[1]) + (1u << s2[-1]) + (1u << s2[EX]) + (1u << s2[-EX]) +
+                              (1u << s2[EX * EY]) + (1u << s2[-EX * EY]);
+          sCnt[r] = make_uint2(c1, c2);
+          const uint32_t e1 = c1 & 0x0f0f0f0fu, o1 = (c1 >> 4) & 0x0f0f0f0fu;
+          const uint32_t e2 = c2 & 0x0f0f0f0fu, o2 = (c2 >> 4) & 0x0f0f0f0fu;
+          // Row of q's own species (rows of 8; the vacancy's row is finite
+          // and unused, a vacancy never being a target).
+          const Real *t1 = sHs1 + 2 * s2[0], *t2 = sHs2 + 2 * s2[0];
+          Real g = Real(0);
+#pragma unroll
+          for (int s = 1; s < S; ++s)
+            g = fma(count_of<Real>(e2, o2, s), t2[s], fma(count_of<Real>(e1, o1, s), t1[s], g));
+          if constexpr (SW::kFactor) {
+            sE[r] = SW::ex(g);
+            if (WITH_EA) sH[r] = g;
+          } else {
+            sE[r] = g;
+          }
+        }
+      }
+    }
   }
   __syncthreads();
 
@@ -326,10 +372,9 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
   // vacancy site for every mover species comes from its counts, with the
   // same chain as above.
   if constexpr (sizeof(Real) == 8) {
-    // binary64: one lane per site forms the site terms (planes of NT), then
-    // four lanes per site combine them with the target terms, two
-    // candidates each, so that the costly exponentials run in short
-    // independent chains.
+    // binary64: one lane per site forms the site factors (planes of NT),
+    // then four lanes per site combine them with the target factors, two
+    // candidates each.
     Real *sTs = sT, *sGs = sT + NA * Sh::NT;
     for (int t = tid; t < Sh::NT; t += kSweepThreads) {
       const int cx = t % TX;
@@ -341,22 +386,25 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
       const int sp = socc[oidx(b, cx, cy, cz)] >> 2;
       const int ip = b * HV + ((cz + b) * HY + (cy + b)) * HX + (cx + b);
       const uint2 cn = sCnt[ip];
+      const uint32_t e1 = cn.x & 0x0f0f0f0fu, o1 = (cn.x >> 4) & 0x0f0f0f0fu;
+      const uint32_t e2 = cn.y & 0x0f0f0f0fu, o2 = (cn.y >> 4) & 0x0f0f0f0fu;
       Real g[NA];
 #pragma unroll
       for (int A = 0; A < NA; ++A) g[A] = Real(0);
 #pragma unroll
       for (int s = 1; s < S; ++s) {
-        const Real n1 = (Real)nib(cn.x, s), n2 = (Real)nib(cn.y, s);
+        const Real n1 = count_of<Real>(e1, o1, s), n2 = count_of<Real>(e2, o2, s);
 #pragma unroll
-        for (int A = 0; A < NA; ++A) g[A] = fma(n2, sDs2[A * S + s], fma(n1, sDs1[A * S + s], g[A]));
+        for (int A = 0; A < NA; ++A) g[A] = fma(n2, sHs2[A * 8 + s], fma(n1, sHs1[A * 8 + s], g[A]));
       }
 #pragma unroll
       for (int A = 0; A < NA; ++A) {
-        sTs[A * Sh::NT + t] = SW::site(sC[A * S + sp], h, g[A]);
+        sTs[A * Sh::NT + t] = SW::ex(sC[A * S + sp] - g[A]);
         if (WITH_EA) sGs[A * Sh::NT + t] = g[A];
       }
     }
     __syncthreads();
+    const Real inv_h = SW::inv_h(d);
     constexpr int LPS = 8 / VW;
     for (int it = tid; it < Sh::NT * LPS; it += kSweepThreads) {
       const int t = it / LPS, part = it % LPS;
@@ -379,11 +427,11 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
         const int A = s1[px + py * EX + pz * (EX * EY)] >> 2;
         const int Ac = min(A, NA - 1);
         const int ij = ij0 + (pz * HY + py) * HX + px;
-        const Real ts = A == V ? SW::masked_site() : sTs[Ac * Sh::NT + t];
-        w[c] = SW::rate(ts, sE[ij]);
+        const Real ts = A == V ? Real(0) : sTs[Ac * Sh::NT + t];
+        w[c] = ts * sE[ij];
         if (WITH_EA)
           we[c] = A == V ? inf_of<Real>()
-                         : se0[Ac] + Real(0.5) * ((sGs[Ac * Sh::NT + t] - sH[ij]) + sK[Ac * S + sp]);
+                         : se0[Ac] + Real(0.5) * ((sGs[Ac * Sh::NT + t] - sH[ij]) * inv_h + sK[Ac * S + sp]);
       }
       const size_t site = (unsigned)(b * ncell + (gz * ly + gy) * lx + gx);
       __builtin_nontemporal_store(w, (vecw *)(rates + site * 8) + part);
@@ -391,61 +439,69 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
     }
     return;
   }
-  // binary32: one lane per site; the grid-uniform tables sit in scalar
-  // registers and the site terms in a per-lane LDS table.
-  const Real *Ds1 = Tab<Real>::Ds1(d), *Ds2 = Tab<Real>::Ds2(d);
+  // binary32: one lane per site; the field tables sit in scalar registers
+  // and the site terms in a per-lane LDS table indexed by the target's code
+  // (stored as 4*code, so that code * kSweepThreads is a single shift of
+  // it); the vacancy's entry is -inf, which makes a masked rate exactly +0.
+  const Real inv_h = SW::inv_h(d);
   Real *myT = sT + tid;
-  myT[NA * kSweepThreads] = SW::masked_site();  // code of the vacancy
-  for (int t = tid; t < Sh::NT; t += kSweepThreads) {
-    const int cx = t % TX;
-    const int row = t / TX;
-    const int cy = row % TY;
-    const int bz = row / TY;
-    const int cz = bz % TZ;
-    const int b = bz / TZ;
-    const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
-    if (gx >= lx || gy >= ly || gz >= lz) continue;
+  myT[NA * kSweepThreads] = -__builtin_huge_valf();  // code of the vacancy: a zero rate
+  // A workgroup's threads cover one sublattice of the brick: the cell of a
+  // thread is fixed and the sublattice is the step.
+  static_assert(sizeof(Real) == 8 || TX * TY * TZ == kSweepThreads, "one brick sublattice per pass");
+  const int cx = tid % TX, cy = (tid / TX) % TY, cz = tid / (TX * TY);
+  const int gx = x0 + cx, gy = y0 + cy, gz = z0 + cz;
+  if (gx >= lx || gy >= ly || gz >= lz) return;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
     const int sp = socc[oidx(b, cx, cy, cz)] >> 2;
     const int ip = b * HV + ((cz + b) * HY + (cy + b)) * HX + (cx + b);
     const int ij0 = (1 - b) * HV + (cz * HY + cy) * HX + cx;
     const uint8_t *s1 = socc + oidx(1 - b, cx - 1 + b, cy - 1 + b, cz - 1 + b);
     const uint2 cn = sCnt[ip];
+    const uint32_t e1 = cn.x & 0x0f0f0f0fu, o1 = (cn.x >> 4) & 0x0f0f0f0fu;
+    const uint32_t e2 = cn.y & 0x0f0f0f0fu, o2 = (cn.y >> 4) & 0x0f0f0f0fu;
     Real g[NA];
 #pragma unroll
     for (int A = 0; A < NA; ++A) g[A] = Real(0);
 #pragma unroll
     for (int s = 1; s < S; ++s) {
-      const Real n1 = (Real)nib(cn.x, s), n2 = (Real)nib(cn.y, s);
+      const Real n1 = count_of<Real>(e1, o1, s), n2 = count_of<Real>(e2, o2, s);
 #pragma unroll
-      for (int A = 0; A < NA; ++A) g[A] = fma(n2, Ds2[A * S + s], fma(n1, Ds1[A * S + s], g[A]));
+      for (int A = 0; A < NA; ++A) g[A] = fma(n2, H2[A * 8 + s], fma(n1, H1[A * 8 + s], g[A]));
     }
 #pragma unroll
-    for (int A = 0; A < NA; ++A) myT[A * kSweepThreads] = SW::site(sC[A * S + sp], h, g[A]);
+    for (int A = 0; A < NA; ++A) myT[A * kSweepThreads] = sC[A * S + sp] - g[A];
     // Site indices stay below 2^31 (checked at create).
     const size_t site = (unsigned)(b * ncell + (gz * ly + gy) * lx + gx);
     vecw *out = (vecw *)(rates + site * 8);
     vecw *oe = WITH_EA ? (vecw *)(ea + site * 8) : nullptr;
+    // All 8 rates first, then the row's stores back to back: a 128-byte
+    // line is covered by the two store instructions of one wavefront, and
+    // issuing them together lets the line be written to HBM once.
     constexpr int NVEC = 8 / VW;
+    vecw w[NVEC], we[NVEC];
 #pragma unroll
-    for (int v = 0; v < NVEC; ++v) {
-      vecw w, we;
+    for (int k = 0; k < 8; ++k) {
+      const int px = (k >> 2) & 1, py = (k >> 1) & 1, pz = k & 1;
+      const int A4 = s1[px + py * EX + pz * (EX * EY)];  // 4 * code
+      const int ij = ij0 + (pz * HY + py) * HX + px;
+      w[k / VW][k % VW] = SW::ex(myT[A4 * (kSweepThreads / 4)] + sE[ij]);
+      if (WITH_EA) {
+        const int A = A4 >> 2;
+        Real ga = g[0];
 #pragma unroll
-      for (int c = 0; c < VW; ++c) {
-        const int k = v * VW + c;
-        const int px = (k >> 2) & 1, py = (k >> 1) & 1, pz = k & 1;
-        const int A = s1[px + py * EX + pz * (EX * EY)] >> 2;
-        const int ij = ij0 + (pz * HY + py) * HX + px;
-        w[c] = SW::rate(myT[A * kSweepThreads], sE[ij]);
-        if (WITH_EA) {
-          Real ga = g[0];
-#pragma unroll
-          for (int m = 1; m < NA; ++m) ga = A == m ? g[m] : ga;
-          const int Ac = min(A, NA - 1);
-          we[c] = A == V ? inf_of<Real>() : se0[Ac] + Real(0.5) * ((ga - sH[ij]) + sK[Ac * S + sp]);
-        }
+        for (int m = 1; m < NA; ++m) ga = A == m ? g[m] : ga;
+        const int Ac = min(A, NA - 1);
+        we[k / VW][k % VW] =
+            A == V ? inf_of<Real>() : se0[Ac] + Real(0.5) * ((ga - sE[ij]) * inv_h + sK[Ac * S + sp]);
       }
-      __builtin_nontemporal_store(w, out + v);
-      if (WITH_EA) __builtin_nontemporal_store(we, oe + v);
+    }
+#pragma unroll
+    for (int v = 0; v < NVEC; ++v) __builtin_nontemporal_store(w[v], out + v);
+    if (WITH_EA) {
+#pragma unroll
+      for (int v = 0; v < NVEC; ++v) __builtin_nontemporal_store(we[v], oe + v);
     }
   }
 }
@@ -488,8 +544,10 @@ template <int S, class Real>
 static hipError_t launch_sweep_s(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                                  void *rates, void *ea, hipStream_t stream) {
   // binary64 takes the narrower brick so that several workgroups share a CU
-  if (sizeof(Real) == 8) return launch_sweep<16, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
-  return launch_sweep<32, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
+  if constexpr (sizeof(Real) == 8)
+    return launch_sweep<16, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
+  else
+    return launch_sweep<32, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
 }
 
 template <class Real>
@@ -510,6 +568,10 @@ static hipError_t launch_sweep_r(const LatDesc *d_desc, const LatDesc &h, const 
 hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                             int precision, void *rates, void *ea, hipStream_t stream) {
   if (precision == AKMC_FP32) return launch_sweep_r<float>(d_desc, h, occ, rates, ea, stream);
+  // The binary64 sweep's factors must stay inside the exponent range; tables
+  // that could leave it take the per-candidate kernel over every site.
+  if (!h.sweep_factor_ok)
+    return launch_rates_sites(d_desc, h, occ, nullptr, 2 * h.ncell, precision, rates, ea, stream);
   return launch_sweep_r<double>(d_desc, h, occ, rates, ea, stream);
 }
 

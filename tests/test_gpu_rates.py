@@ -136,3 +136,37 @@ def test_all_sites_rates_only_equal_rates_with_barriers(dims, S, nv, seed, preci
     torch.cuda.synchronize()
     lat.close()
     assert torch.equal(r, r_only)
+
+
+
+@pytest.mark.parametrize("scale", [5.0, 6.0])
+def test_all_sites_fp64_wide_exponent_range(oracle_mod, scale):
+    """Pair energies 5x and 6x the usual spread at 300 K (rates from 1e-146
+    to 1e131).  At 5x every binary64 factor of the sweep provably stays
+    below exp(700) and the factored sweep runs near that limit; at 6x the
+    bound is exceeded and ALL_SITES runs the per-candidate kernel over every
+    site instead, bit for bit the SITES mode over the full site list.  Both
+    match the oracle."""
+    import dataclasses
+    import torch
+    banner("all sites fp64 energy scale %.0f" % scale)
+    spec = W.random_lattice(np.random.default_rng(31), (9, 8, 7), 5, 12, solute_total=0.3,
+                            temperature=300.0)
+    spec = dataclasses.replace(spec, eps1=scale * spec.eps1, eps2=scale * spec.eps2)
+    lat = akmc.Lattice(spec, precision=akmc.FP64)
+    r, e = lat.rates(akmc.RATES_ALL_SITES, with_ea=True)
+    sites = np.arange(spec.n_sites, dtype=np.int32)
+    r2, e2 = lat.rates(akmc.RATES_SITES, sites=sites, with_ea=True)
+    torch.cuda.synchronize()
+    if scale == 6.0:
+        assert torch.equal(r, r2) and torch.equal(e, e2)
+    r = r.cpu().numpy()
+    e = e.cpu().numpy()
+    lat.close()
+    with np.errstate(over="ignore", under="ignore"):
+        ro, eo = oracle_mod.Oracle(spec, precision=0).rates_sites(sites)
+    m = ro > 0
+    assert np.all(np.isfinite(ro)) and m.sum() > 0.9 * ro.size
+    assert np.array_equal(r == 0, ~m)
+    assert np.max(np.abs(r[m] - ro[m]) / ro[m]) <= 1e-12
+    assert np.max(np.abs(e[m] - eo[m])) <= 1e-12
