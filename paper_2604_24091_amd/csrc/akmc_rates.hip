@@ -236,11 +236,8 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
     }
   }
 
-  const int ntx = (lx + TX - 1) / TX, nty = (ly + TY - 1) / TY;
-  const int tile = blockIdx.x;
-  const int x0 = (tile % ntx) * TX;
-  const int y0 = ((tile / ntx) % nty) * TY;
-  const int z0 = (tile / (ntx * nty)) * TZ;
+  // One workgroup per brick of a 3-D grid of bricks.
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
 
   // Phase 1: occupancy brick of both sublattices, as 4*species (the shift of
   // that species' count nibble).  One conditional wrap per axis suffices
@@ -250,14 +247,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
   const bool simple = lx >= TX + PX && ly > TY + 2 && lz > TZ + 2;
   static_assert(TX % 8 == 0 && PX % 8 == 0, "brick rows must start on 8-byte boundaries");
   if (simple && (lx & 7) == 0) {
-    // Eight lanes per row (the first EX/8 load), one pass of the workgroup
-    // per sublattice: the indices are formed once and both sublattices'
-    // loads are in flight together.  With lx a multiple of 8 a vector never
-    // straddles the periodic seam.
+    // QW lanes per row of one sublattice, the first QW*EY*EZ lanes (whole
+    // wavefronts; the others skip): the indices are formed once and both
+    // sublattices' loads are in flight together.  With lx a multiple of 8 a
+    // vector never straddles the periodic seam.
     constexpr int QW = EX / 8;
-    static_assert(QW <= 8 && EY * EZ * 8 == kSweepThreads, "one pass per sublattice");
-    const int w = tid & 7, ey = (tid >> 3) % EY, ez = (tid >> 3) / EY;
-    if (w < QW) {
+    static_assert(QW * EY * EZ <= kSweepThreads, "one pass per sublattice");
+    if (tid < QW * EY * EZ) {
+      const int row = tid / QW, w = tid - row * QW;
+      const int ey = row % EY, ez = row / EY;
       int gx = x0 - PX + 8 * w, gy = y0 + ey - 2, gz = z0 + ez - 2;
       gx += gx < 0 ? lx : 0;  gx -= gx >= lx ? lx : 0;
       gy += gy < 0 ? ly : 0;  gy -= gy >= ly ? ly : 0;
@@ -527,15 +525,15 @@ template <int TX, int TY, int TZ, int S, class Real>
 static hipError_t launch_sweep(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                                void *rates, void *ea, hipStream_t stream) {
   using Sh = SweepShape<TX, TY, TZ>;
-  const unsigned tiles = (unsigned)(((h.lx + TX - 1) / TX) * ((h.ly + TY - 1) / TY) *
-                                    ((h.lz + TZ - 1) / TZ));
+  const dim3 tiles((unsigned)((h.lx + TX - 1) / TX), (unsigned)((h.ly + TY - 1) / TY),
+                   (unsigned)((h.lz + TZ - 1) / TZ));
   const size_t lds = Sh::lds_bytes(S, sizeof(Real), ea != nullptr);
   auto k = ea ? k_rates_all<TX, TY, TZ, S, Real, true> : k_rates_all<TX, TY, TZ, S, Real, false>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k, dim3(tiles), dim3(kSweepThreads), lds, stream, d_desc, occ, (Real *)rates,
+  hipLaunchKernelGGL(k, tiles, dim3(kSweepThreads), lds, stream, d_desc, occ, (Real *)rates,
                      (Real *)ea);
   return hipGetLastError();
 }
@@ -547,7 +545,7 @@ static hipError_t launch_sweep_s(const LatDesc *d_desc, const LatDesc &h, const 
   if constexpr (sizeof(Real) == 8)
     return launch_sweep<16, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
   else
-    return launch_sweep<32, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
+    return launch_sweep<16, 4, 8, S, Real>(d_desc, h, occ, rates, ea, stream);
 }
 
 template <class Real>

@@ -14,7 +14,10 @@ pytestmark = pytest.mark.gpu
 
 CASES = [((3, 3, 3), 3, 4, 1), ((5, 4, 6), 5, 12, 2), ((12, 12, 12), 5, 40, 3),
          ((37, 5, 9), 5, 30, 4), ((33, 34, 35), 4, 100, 5), ((20, 7, 11), 8, 50, 6),
-         ((40, 9, 6), 2, 20, 7), ((44, 7, 7), 5, 20, 8), ((41, 7, 6), 3, 10, 9)]
+         ((40, 9, 6), 2, 20, 7), ((44, 7, 7), 5, 20, 8), ((41, 7, 6), 3, 10, 9),
+         # staging paths of the sweep: 8-byte rows at the smallest edges that
+         # allow them, with wraps on every axis; dword rows
+         ((24, 7, 11), 5, 10, 10), ((40, 12, 16), 4, 30, 11), ((28, 9, 13), 5, 15, 12)]
 
 
 def _compare(spec, oracle_mod, precision, mode):
