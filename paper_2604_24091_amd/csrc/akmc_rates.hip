@@ -148,6 +148,13 @@ __device__ __forceinline__ Real count_of(uint32_t ev, uint32_t od, int s) {
   return (Real)(((s & 1) ? od : ev) >> (8 * (s >> 1)) & 0xffu);
 }
 
+// Whether either shell holds a vacancy (code V).  Vacancies are a tiny
+// fraction of the sites, so the field chains add the vacancy terms last and
+// only where a lane needs them: a wavefront without such a lane skips them.
+__device__ __forceinline__ bool has_vacancy(uint32_t c1, uint32_t c2, int V) {
+  return ((c1 | c2) >> (4 * V) & 15u) != 0u;
+}
+
 constexpr int kSweepThreads = 512;
 
 template <int TX, int TY, int TZ>
@@ -352,8 +359,10 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
           const Real *t1 = sHs1 + 2 * s2[0], *t2 = sHs2 + 2 * s2[0];
           Real g = Real(0);
 #pragma unroll
-          for (int s = 1; s < S; ++s)
+          for (int s = 1; s < V; ++s)
             g = fma(count_of<Real>(e2, o2, s), t2[s], fma(count_of<Real>(e1, o1, s), t1[s], g));
+          if (has_vacancy(c1, c2, V))
+            g = fma(count_of<Real>(e2, o2, V), t2[V], fma(count_of<Real>(e1, o1, V), t1[V], g));
           if constexpr (SW::kFactor) {
             sE[r] = SW::ex(g);
             if (WITH_EA) sH[r] = g;
@@ -390,10 +399,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
 #pragma unroll
       for (int A = 0; A < NA; ++A) g[A] = Real(0);
 #pragma unroll
-      for (int s = 1; s < S; ++s) {
+      for (int s = 1; s < V; ++s) {
         const Real n1 = count_of<Real>(e1, o1, s), n2 = count_of<Real>(e2, o2, s);
 #pragma unroll
         for (int A = 0; A < NA; ++A) g[A] = fma(n2, sHs2[A * 8 + s], fma(n1, sHs1[A * 8 + s], g[A]));
+      }
+      if (has_vacancy(cn.x, cn.y, V)) {
+        const Real n1 = count_of<Real>(e1, o1, V), n2 = count_of<Real>(e2, o2, V);
+#pragma unroll
+        for (int A = 0; A < NA; ++A) g[A] = fma(n2, sHs2[A * 8 + V], fma(n1, sHs1[A * 8 + V], g[A]));
       }
 #pragma unroll
       for (int A = 0; A < NA; ++A) {
@@ -463,10 +477,15 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
 #pragma unroll
     for (int A = 0; A < NA; ++A) g[A] = Real(0);
 #pragma unroll
-    for (int s = 1; s < S; ++s) {
+    for (int s = 1; s < V; ++s) {
       const Real n1 = count_of<Real>(e1, o1, s), n2 = count_of<Real>(e2, o2, s);
 #pragma unroll
       for (int A = 0; A < NA; ++A) g[A] = fma(n2, H2[A * 8 + s], fma(n1, H1[A * 8 + s], g[A]));
+    }
+    if (has_vacancy(cn.x, cn.y, V)) {
+      const Real n1 = count_of<Real>(e1, o1, V), n2 = count_of<Real>(e2, o2, V);
+#pragma unroll
+      for (int A = 0; A < NA; ++A) g[A] = fma(n2, H2[A * 8 + V], fma(n1, H1[A * 8 + V], g[A]));
     }
 #pragma unroll
     for (int A = 0; A < NA; ++A) myT[A * kSweepThreads] = sC[A * S + sp] - g[A];
