@@ -46,8 +46,9 @@
  *     (n:int64, from:int32, to:int32) per event.
  *
  * Precision: fp64 throughout by default.  A second mode computes energy
- * change, barrier and rate in binary32 (fmaf chain, binary32 division,
- * expf) and widens the rate to binary64 before any sum; it exists so that
+ * change, barrier and rate in binary32 (fmaf chain; rate nu * 2^(Ea * c)
+ * with c = -log2(e) / kT by one binary32 division, exp2f) and widens the
+ * rate to binary64 before any sum; it exists so that
  * the oracle takes selection decisions in the same precision as a binary32
  * rate kernel.
  *
@@ -206,8 +207,8 @@ void orc_candidate(const orc_params *p, const uint8_t *occ, int32_t i, int k,
         for (int s = 0; s < S; s++) acc = fmaf((float)dn2[s], (float)dtab(p->eps2, S, A, s), acc);
         float ea = (float)p->e0[A] + 0.5f * acc;
         float kt = (float)(p->kb * p->temperature);
-        float x = -(ea / kt);
-        float r = (float)p->nu * expf(x);
+        float c = -1.44269504088896341f / kt;
+        float r = (float)p->nu * exp2f(ea * c);
         *ea_out = (double)ea;
         *rate_out = (double)r;
     }

@@ -151,9 +151,11 @@ __device__ __forceinline__ double rate_from_barrier(double ea, double nu, double
   double x = -(ea / kT);
   return nu * exp(x);
 }
+// binary32: nu * 2^(Ea * (-log2(e) / kT)) on the hardware base-2
+// exponential (about 1 ulp); where the function is inlined into a loop the
+// scale is computed once.
 __device__ __forceinline__ float rate_from_barrier(float ea, float nu, float kT) {
-  float x = -(ea / kT);
-  return nu * expf(x);
+  return nu * __builtin_amdgcn_exp2f(ea * (-1.44269504088896341f / kT));
 }
 
 }  // namespace akmc
