@@ -83,7 +83,8 @@ struct LoopArgs {
 // children: level 1 over slot totals, level l+1 over the last partial of
 // each level-l group, until one group of at most 8 nodes remains.
 constexpr int kBoxBytes = 352;   // 7x7x7 footprint box, padded to 16
-constexpr int kMaxLevels = 4;
+constexpr int kMaxLevels = 3;
+static_assert(AKMC_MAX_VACANCIES <= 8 * 8 * 8, "three levels of groups of 8 cover every slot");
 
 struct GroupLayout {
   int nv_max, G, fp32, nlev_max;
