@@ -141,8 +141,7 @@ template <> struct Sweep<float> {
 };
 
 // Species count s of a packed nibble count vector c, as a real, from the
-// even (c & 0x0f0f0f0f) or odd ((c >> 4) & 0x0f0f0f0f) nibbles: one byte
-// conversion per count.
+// even (c & 0x0f0f0f0f) or odd ((c >> 4) & 0x0f0f0f0f) nibbles.
 template <class Real>
 __device__ __forceinline__ Real count_of(uint32_t ev, uint32_t od, int s) {
   return (Real)(((s & 1) ? od : ev) >> (8 * (s >> 1)) & 0xffu);
@@ -168,10 +167,10 @@ struct SweepShape {
   static constexpr int HX = TX + 1, HY = TY + 1, HZ = TZ + 1, HV = HX * HY * HZ;  // field region
   static constexpr int NT = 2 * TX * TY * TZ;                                     // brick sites
   static constexpr int OCC_BYTES = (2 * EV + 15) & ~15;
-  // per region site: bond counts (2 words), the target factor and (barrier
-  // output only) its field; site factors: binary32 per lane (S planes of
-  // kSweepThreads), binary64 per brick site (S-1 planes of NT, twice with
-  // the barrier output)
+  // per region site: bond counts (2 words), the target term (binary32) or
+  // factor (binary64) and, for the binary64 barrier output, its field; site
+  // terms: binary32 per lane (S planes of kSweepThreads), binary64 factors
+  // per brick site (S-1 planes of NT, twice with the barrier output)
   __host__ __device__ static constexpr size_t terms(int S, size_t real, bool with_ea) {
     return real == 4 ? (size_t)S * kSweepThreads : (size_t)(S - 1) * NT * (with_ea ? 2 : 1);
   }
