@@ -28,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -42,10 +43,16 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_rates_all_rpv_4m_traffic.jso
 
 
 def kernel_source_hash():
+    """Hash of the sweep's sources without comments and layout, so that the
+    stored traffic counters stay valid across edits that leave the code
+    unchanged."""
     h = hashlib.sha256()
     for f in ("akmc_rates.hip", "akmc_device.hpp", "akmc_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2604_24091_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2604_24091_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
