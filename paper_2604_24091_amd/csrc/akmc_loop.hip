@@ -174,7 +174,9 @@ __host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
   return (size_t)2 * kHid * mlp_k1(S) + (size_t)2 * kHid * kHid + 64 * 32 + 2 * 16 * kHid + 64 * 4 + 40 * 4;
 }
 
-template <int G, class Real, bool MLP = false>
+// KL: the most tree levels of any lattice of the launch (at most
+// kMaxLevels); the level loops are unrolled that far.
+template <int G, class Real, bool MLP = false, int KL = kMaxLevels>
 struct Runner {
   LoopArgs a;
   Group<G> gp;
@@ -288,9 +290,9 @@ struct Runner {
   __device__ double update_path(int v, double gv) {
     const int c = gp.gl & 7;
     const bool worker = gp.gl < 8;
-    double x[kMaxLevels + 1];
+    double x[KL + 1];
 #pragma unroll
-    for (int l = 1; l <= kMaxLevels; ++l) {
+    for (int l = 1; l <= KL; ++l) {
       x[l] = 0.0;
       if (l <= nlev) {
         const int u = 8 * (v >> (3 * l)) + c;
@@ -308,7 +310,7 @@ struct Runner {
     }
     double fresh = gv;
 #pragma unroll
-    for (int l = 1; l <= kMaxLevels; ++l) {
+    for (int l = 1; l <= KL; ++l) {
       if (l <= nlev) {
         const int g = v >> (3 * l);
         if (c == ((v >> (3 * (l - 1))) & 7)) x[l] = fresh;
@@ -529,7 +531,7 @@ struct Runner {
     const bool full = a.refresh_full != 0;
 
     nlev = 1;
-    while (nl(nlev) > 8 && nlev < kMaxLevels) ++nlev;
+    while (nl(nlev) > 8 && nlev < KL) ++nlev;
 
     double t = st->t;
     int64_t n = st->n;
@@ -581,7 +583,7 @@ struct Runner {
       int node = 0;
       bool skip = false;
 #pragma unroll
-      for (int l = kMaxLevels; l >= 0; --l) {
+      for (int l = KL; l >= 0; --l) {
         if (l > nlev) continue;
         if (skip) {
           skip = false;
@@ -800,7 +802,7 @@ struct Runner {
   }
 };
 
-template <int G, int WAVES, bool FP32, bool MLP = false>
+template <int G, int WAVES, bool FP32, bool MLP = false, int KL = kMaxLevels>
 __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayout L) {
   using Real = typename std::conditional<FP32, float, double>::type;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -834,7 +836,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayo
     }
   }
 
-  Runner<G, Real, MLP> run(a, L, gp, foot, mine);
+  Runner<G, Real, MLP, KL> run(a, L, gp, foot, mine);
   for (;;) {
     int idx = 0;
     if (gp.gl == 0) idx = atomicAdd(a.queue, 1);
@@ -860,7 +862,10 @@ template <int G, int W, bool FP32>
 static hipError_t launch_one(const LoopArgs &a, const Schedule &s, hipStream_t stream) {
   const GroupLayout L = make_layout(a.nv_max, G, FP32 ? 1 : 0);
   const size_t lds = (size_t)L.bytes * (64 / G) * W;
-  auto kern = k_event_loop<G, W, FP32>;
+  // Lattices of at most 64 slots need two tree levels: a shorter unrolled
+  // descent and re-sum.
+  static_assert(kMaxLevels == 3, "level variants");
+  auto kern = L.nlev_max <= 2 ? k_event_loop<G, W, FP32, false, 2> : k_event_loop<G, W, FP32, false, 3>;
   if (lds > 65536) {
     hipError_t e = hipFuncSetAttribute((const void *)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
