@@ -171,7 +171,8 @@ struct MlpLds {
 };
 
 __host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
-  return (size_t)2 * kHid * mlp_k1(S) + (size_t)2 * kHid * kHid + 64 * 32 + 2 * 16 * kHid + 64 * 4 + 40 * 4;
+  return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + (size_t)2 * kHid * kLdH + 64 * 32 + 2 * 16 * kLdH + 64 * 4 +
+         40 * 4;
 }
 
 // KL: the most tree levels of any lattice of the launch (at most
@@ -210,16 +211,13 @@ struct Runner {
       sigma = hdr->sigma;
       unsigned char *b = lds + L.bytes;
       ml.w1t = (unsigned short *)b;
-      ml.w2t = ml.w1t + kHid * k1;
-      ml.senv = (uint8_t *)(ml.w2t + kHid * kHid);
+      ml.w2t = ml.w1t + kHid * mlp_ld1(k1);
+      ml.senv = (uint8_t *)(ml.w2t + kHid * kLdH);
       ml.hst = (unsigned short *)(ml.senv + 64 * 32);
-      ml.yb = (float *)(ml.hst + 16 * kHid);
+      ml.yb = (float *)(ml.hst + 16 * kLdH);
       ml.ood = (int *)(ml.yb + 64);
-      const unsigned char *src1 = a.mlp_blob + mlay.w1t, *src2 = a.mlp_blob + mlay.w2t;
-      for (int o = gp.gl * 16; o < 2 * kHid * k1; o += 64 * 16)
-        *(uint4 *)((unsigned char *)ml.w1t + o) = *(const uint4 *)(src1 + o);
-      for (int o = gp.gl * 16; o < 2 * kHid * kHid; o += 64 * 16)
-        *(uint4 *)((unsigned char *)ml.w2t + o) = *(const uint4 *)(src2 + o);
+      stage_rows(ml.w1t, (const unsigned short *)(a.mlp_blob + mlay.w1t), kHid, k1, mlp_ld1(k1), gp.gl, G);
+      stage_rows(ml.w2t, (const unsigned short *)(a.mlp_blob + mlay.w2t), kHid, kHid, kLdH, gp.gl, G);
       if (gp.gl < 40) ml.ood[gp.gl] = hdr->ood_valid ? hdr->ood_max[gp.gl >> 3][gp.gl & 7] : 64;
       gsync();
     }

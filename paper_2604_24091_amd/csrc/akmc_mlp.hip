@@ -133,14 +133,11 @@ __global__ __launch_bounds__(256) void k_ood_fit(const uint8_t *__restrict__ env
 
 // ------------------------------------------------------ weight staging
 
-__device__ __forceinline__ void stage_bytes(unsigned char *dst, const unsigned char *src, size_t nbytes) {
-  for (size_t o = threadIdx.x * 16; o < nbytes; o += (size_t)blockDim.x * 16)
-    *(uint4 *)(dst + o) = *(const uint4 *)(src + o);
-}
-
 // ------------------------------------------------------ bulk inference
 
 constexpr int kFwdWaves = 8;
+// Per wavefront: 16 rows of 32 codes, then the 16-row activation tile.
+constexpr int kWaveBytes = 512 + 2 * 16 * kLdH;
 
 __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const unsigned char *__restrict__ blob,
                                                                 const uint8_t *__restrict__ env,
@@ -150,12 +147,12 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const unsigned c
   const int S = hdr->S, k1 = hdr->k1;
   const MlpLayout L = mlp_layout(S);
   unsigned short *w1t = (unsigned short *)mlp_lds;
-  unsigned short *w2t = w1t + kHid * k1;
-  unsigned char *per_wave = (unsigned char *)(w2t + kHid * kHid);
-  stage_bytes((unsigned char *)w1t, blob + L.w1t, (size_t)2 * kHid * k1);
-  stage_bytes((unsigned char *)w2t, blob + L.w2t, (size_t)2 * kHid * kHid);
+  unsigned short *w2t = w1t + kHid * mlp_ld1(k1);
+  unsigned char *per_wave = (unsigned char *)(w2t + kHid * kLdH);
+  stage_rows(w1t, (const unsigned short *)(blob + L.w1t), kHid, k1, mlp_ld1(k1), threadIdx.x, blockDim.x);
+  stage_rows(w2t, (const unsigned short *)(blob + L.w2t), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  uint8_t *senv = per_wave + wave * (512 + 4096);
+  uint8_t *senv = per_wave + wave * kWaveBytes;
   unsigned short *hst = (unsigned short *)(senv + 512);
   const float *prm = (const float *)(blob + L.params);
   const float mu = hdr->mu, sigma = hdr->sigma;
@@ -232,15 +229,15 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_partial(TrainArg
   const int S = hdr->S, k1 = hdr->k1, np = hdr->nparams;
   const MlpLayout L = mlp_layout(S);
   unsigned short *w1t = (unsigned short *)mlp_lds;
-  unsigned short *w2t = w1t + kHid * k1;
-  unsigned short *w2r = w2t + kHid * kHid;
-  unsigned char *per_wave = (unsigned char *)(w2r + kHid * kHid);
-  stage_bytes((unsigned char *)w1t, ta.blob + L.w1t, (size_t)2 * kHid * k1);
-  stage_bytes((unsigned char *)w2t, ta.blob + L.w2t, (size_t)2 * kHid * kHid);
-  stage_bytes((unsigned char *)w2r, ta.blob + L.w2r, (size_t)2 * kHid * kHid);
+  unsigned short *w2t = w1t + kHid * mlp_ld1(k1);
+  unsigned short *w2r = w2t + kHid * kLdH;
+  unsigned char *per_wave = (unsigned char *)(w2r + kHid * kLdH);
+  stage_rows(w1t, (const unsigned short *)(ta.blob + L.w1t), kHid, k1, mlp_ld1(k1), threadIdx.x, blockDim.x);
+  stage_rows(w2t, (const unsigned short *)(ta.blob + L.w2t), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
+  stage_rows(w2r, (const unsigned short *)(ta.blob + L.w2r), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int r = l & 15, q = l >> 4;
-  uint8_t *senv = per_wave + wave * (512 + 4096);
+  uint8_t *senv = per_wave + wave * kWaveBytes;
   unsigned short *hst = (unsigned short *)(senv + 512);
   const float *prm = (const float *)(ta.blob + L.params);
   const float mu = hdr->mu, sigma = hdr->sigma;
@@ -322,7 +319,7 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_partial(TrainArg
     for (int i = 0; i < 4; ++i) {
       const unsigned short hb = f2bf(dz2[c][i]);
       dz2b[c][i] = (short)hb;
-      hst[(4 * q + i) * kHid + 16 * c + r] = hb;
+      hst[(4 * q + i) * kLdH + 16 * c + r] = hb;
     }
 #pragma unroll
   for (int ti = 0; ti < 8; ++ti) {
@@ -346,10 +343,10 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_partial(TrainArg
   for (int c = 0; c < 8; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const bf16x8 a = *(const bf16x8 *)(hst + r * kHid + 32 * t + 8 * q);
+    const bf16x8 a = *(const bf16x8 *)(hst + r * kLdH + 32 * t + 8 * q);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const bf16x8 b = *(const bf16x8 *)(w2r + (16 * c + r) * kHid + 32 * t + 8 * q);
+      const bf16x8 b = *(const bf16x8 *)(w2r + (16 * c + r) * kLdH + 32 * t + 8 * q);
       acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
     }
   }
@@ -480,9 +477,9 @@ __global__ __launch_bounds__(256) void k_mlp_init(unsigned char *__restrict__ bl
 
 // ------------------------------------------------------------ launchers
 
-static size_t fwd_lds(int S) { return (size_t)2 * kHid * mlp_k1(S) + 2 * kHid * kHid + kFwdWaves * (512 + 4096); }
+static size_t fwd_lds(int S) { return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + 2 * kHid * kLdH + kFwdWaves * kWaveBytes; }
 static size_t train_lds(int S) {
-  return (size_t)2 * kHid * mlp_k1(S) + 2 * (size_t)2 * kHid * kHid + kTrainWaves * (512 + 4096);
+  return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + 2 * (size_t)2 * kHid * kLdH + kTrainWaves * kWaveBytes;
 }
 
 hipError_t launch_env_encode(const LatDesc *d_desc, const uint8_t *occ, const int32_t *sites,

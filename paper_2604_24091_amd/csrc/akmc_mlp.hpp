@@ -17,6 +17,12 @@
 namespace akmc {
 
 constexpr int kHid = 128;
+// LDS row pitch of staged weights and activations, in bf16 elements: 16
+// bytes beyond the data, so that the 16 lanes of a row group, which read
+// 16 consecutive rows at the same column, fall on different banks.
+constexpr int kPad = 8;
+constexpr int kLdH = kHid + kPad;
+__host__ __device__ inline int mlp_ld1(int k1) { return k1 + kPad; }
 constexpr int kSlots = 27;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -103,8 +109,8 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 
 // Forward pass of 16 rows by one wavefront.
 //   env:   LDS, 16 rows x 32 bytes of species codes (27 used)
-//   w1t:   LDS, bf16 [128][k1]   (output feature major)
-//   w2t:   LDS, bf16 [128][128]
+//   w1t:   LDS, bf16 [128][k1 + kPad]   (output feature major, padded rows)
+//   w2t:   LDS, bf16 [128][kLdH]
 //   hst:   LDS, bf16 [16][128] staging of one activation tile
 //   prm:   binary32 parameter vector (biases, w3, b3)
 // Results per lane (C layout of the 16x16 matrix-core tiles: lane l holds
@@ -112,6 +118,17 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 //   h1b[c][i], h2b[c][i]  bf16 activations; gp1/gp2 gelu'(z) (if GRAD);
 //   y[i] for rows 4*(l/16)+i (sum over all columns, identical in the 16
 //   lanes of a row group).
+// Copies rows x cols bf16 values (cols a multiple of 8) from a dense array
+// into LDS rows of pitch ld, 16 bytes per thread and step.
+__device__ __forceinline__ void stage_rows(unsigned short *dst, const unsigned short *src, int rows,
+                                           int cols, int ld, int tid, int nthreads) {
+  const int per_row = cols / 8;
+  for (int u = tid; u < rows * per_row; u += nthreads) {
+    const int r = u / per_row, c8 = u - r * per_row;
+    *(uint4 *)(dst + r * ld + 8 * c8) = *(const uint4 *)(src + r * cols + 8 * c8);
+  }
+}
+
 template <bool GRAD>
 __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned short *w1t,
                                           const unsigned short *w2t, unsigned short *hst,
@@ -137,7 +154,7 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const bf16x8 b = *(const bf16x8 *)(w1t + (16 * c + r) * k1 + 32 * t + 8 * q);
+      const bf16x8 b = *(const bf16x8 *)(w1t + (16 * c + r) * mlp_ld1(k1) + 32 * t + 8 * q);
       acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
     }
   }
@@ -150,7 +167,7 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
       const unsigned short hb = f2bf(gelu_f(z));
       h1b[c][i] = hb;
       if (GRAD) gp1[c][i] = gelu_grad_f(z);
-      hst[(4 * q + i) * kHid + 16 * c + r] = hb;
+      hst[(4 * q + i) * kLdH + 16 * c + r] = hb;
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -161,10 +178,10 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
   for (int c = 0; c < 8; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const bf16x8 a = *(const bf16x8 *)(hst + r * kHid + 32 * t + 8 * q);
+    const bf16x8 a = *(const bf16x8 *)(hst + r * kLdH + 32 * t + 8 * q);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
-      const bf16x8 b = *(const bf16x8 *)(w2t + (16 * c + r) * kHid + 32 * t + 8 * q);
+      const bf16x8 b = *(const bf16x8 *)(w2t + (16 * c + r) * kLdH + 32 * t + 8 * q);
       acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
     }
   }
