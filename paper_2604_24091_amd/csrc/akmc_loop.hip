@@ -168,11 +168,13 @@ struct MlpLds {
   uint8_t *senv;
   float *yb;
   int *ood;
+  float *pb;  // biases b1, b2, output weights w3 and bias b3 (128, 128, 128, 1)
+  unsigned short *atile;  // one-hot input tile, 16 rows of pitch mlp_ld1(k1)
 };
 
 __host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
   return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + (size_t)2 * kHid * kLdH + 64 * 32 + 2 * 16 * kLdH + 64 * 4 +
-         40 * 4;
+         40 * 4 + (3 * kHid + 1) * 4 + 16 + (size_t)2 * 16 * mlp_ld1(mlp_k1(S));
 }
 
 // KL: the most tree levels of any lattice of the launch (at most
@@ -189,7 +191,7 @@ struct Runner {
   uint8_t *occ;
   // learned barrier
   MlpLds ml;
-  MlpLayout mlay;
+  MlpLayout mlay, play;  // play: offsets of the parameters staged in LDS
   const float *prm;
   float mu, sigma;
   int k1;
@@ -216,9 +218,24 @@ struct Runner {
       ml.hst = (unsigned short *)(ml.senv + 64 * 32);
       ml.yb = (float *)(ml.hst + 16 * kLdH);
       ml.ood = (int *)(ml.yb + 64);
+      ml.pb = (float *)(ml.ood + 40);
+      ml.atile = (unsigned short *)(((uintptr_t)(ml.pb + 3 * kHid + 1) + 15) & ~(uintptr_t)15);
       stage_rows(ml.w1t, (const unsigned short *)(a.mlp_blob + mlay.w1t), kHid, k1, mlp_ld1(k1), gp.gl, G);
       stage_rows(ml.w2t, (const unsigned short *)(a.mlp_blob + mlay.w2t), kHid, kHid, kLdH, gp.gl, G);
       if (gp.gl < 40) ml.ood[gp.gl] = hdr->ood_valid ? hdr->ood_max[gp.gl >> 3][gp.gl & 7] : 64;
+      // The forward's biases and output weights in LDS, with a layout whose
+      // offsets point there (the weight matrices are staged above).
+      for (int x = gp.gl; x < kHid; x += G) {
+        ml.pb[x] = prm[mlay.ob1 + x];
+        ml.pb[kHid + x] = prm[mlay.ob2 + x];
+        ml.pb[2 * kHid + x] = prm[mlay.ow3 + x];
+      }
+      if (gp.gl == 0) ml.pb[3 * kHid] = prm[mlay.ob3];
+      play = mlay;
+      play.ob1 = 0;
+      play.ob2 = kHid;
+      play.ow3 = 2 * kHid;
+      play.ob3 = 3 * kHid;
       gsync();
     }
 #pragma unroll
@@ -373,7 +390,8 @@ struct Runner {
     for (int t = 0; t < ntiles; ++t) {
       unsigned short h1b[8][4], h2b[8][4];
       float gp1[8][4], gp2[8][4], y[4];
-      mlp_fwd16<false>(ml.senv + t * 16 * 32, ml.w1t, ml.w2t, ml.hst, prm, mlay, S, k1, h1b, h2b,
+      onehot_tile(ml.senv + t * 16 * 32, ml.atile, S, k1, gp.gl);
+      mlp_fwd16<false, true>((const uint8_t *)ml.atile, ml.w1t, ml.w2t, ml.hst, ml.pb, play, S, k1, h1b, h2b,
                        gp1, gp2, y);
       if ((gp.gl & 15) == 0)
 #pragma unroll

@@ -129,7 +129,27 @@ __device__ __forceinline__ void stage_rows(unsigned short *dst, const unsigned s
   }
 }
 
-template <bool GRAD>
+// One-hot input tile of 16 rows (bf16, pitch mlp_ld1(k1)) from 16 rows of
+// 32 species codes (the first kSlots used): the wavefront clears the tile,
+// then sets feature slot*S + code of every (row, slot).
+__device__ __forceinline__ void onehot_tile(const uint8_t *codes, unsigned short *atile, int S, int k1,
+                                            int lane) {
+  const int ld = mlp_ld1(k1);
+  for (int u = lane; u < 16 * ld / 8; u += 64) *(uint4 *)(atile + 8 * u) = make_uint4(0u, 0u, 0u, 0u);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int u = lane; u < 16 * kSlots; u += 64) {
+    const int row = u / kSlots, slot = u - row * kSlots;
+    atile[row * ld + slot * S + codes[row * 32 + slot]] = 0x3F80;  // bf16 1.0
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ATILE: env is the one-hot tile built by onehot_tile instead of codes.
+template <bool GRAD, bool ATILE = false>
 __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned short *w1t,
                                           const unsigned short *w2t, unsigned short *hst,
                                           const float *prm, const MlpLayout &L, int S, int k1,
@@ -145,12 +165,16 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
   const int mg = s_magic(S);
   for (int t = 0; t < nk; ++t) {
     bf16x8 a;
+    if (ATILE) {
+      a = *(const bf16x8 *)((const unsigned short *)env + r * mlp_ld1(k1) + 32 * t + 8 * q);
+    } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int f = 32 * t + 8 * q + i;
-      const int slot = div_s(f, mg), sp = f - slot * S;
-      const bool one = slot < kSlots && env[r * 32 + slot] == sp;
-      a[i] = __builtin_bit_cast(__bf16, (unsigned short)(one ? 0x3F80 : 0));
+      for (int i = 0; i < 8; ++i) {
+        const int f = 32 * t + 8 * q + i;
+        const int slot = div_s(f, mg), sp = f - slot * S;
+        const bool one = slot < kSlots && env[r * 32 + slot] == sp;
+        a[i] = __builtin_bit_cast(__bf16, (unsigned short)(one ? 0x3F80 : 0));
+      }
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
