@@ -162,19 +162,19 @@ __device__ __forceinline__ double eval_box(const uint8_t *box, int k, int V, con
 }
 
 // LDS of the learned barrier (one group per block): bf16 weights, the
-// 64-row code staging, the activation staging tile, outputs, OOD bounds.
+// 64-row code staging, the activation staging tile, outputs, biases and
+// output weights, the one-hot input tile.
 struct MlpLds {
   unsigned short *w1t, *w2t, *hst;
   uint8_t *senv;
   float *yb;
-  int *ood;
   float *pb;  // biases b1, b2, output weights w3 and bias b3 (128, 128, 128, 1)
   unsigned short *atile;  // one-hot input tile, 16 rows of pitch mlp_ld1(k1)
 };
 
 __host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
   return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + (size_t)2 * kHid * kLdH + 64 * 32 + 2 * 16 * kLdH + 64 * 4 +
-         40 * 4 + (3 * kHid + 1) * 4 + 16 + (size_t)2 * 16 * mlp_ld1(mlp_k1(S));
+         (3 * kHid + 1) * 4 + 16 + (size_t)2 * 16 * mlp_ld1(mlp_k1(S));
 }
 
 // KL: the most tree levels of any lattice of the launch (at most
@@ -196,6 +196,10 @@ struct Runner {
   float mu, sigma;
   int k1;
   int64_t n_ood;
+  // Out-of-distribution bounds packed per bond group as nibbles (b | 8) of
+  // the largest count seen per species (15: no bound), and the mask of
+  // moving species seen in training.
+  uint32_t oodw[4], seen;
   double top_q;   // lane c < 8: partial c of the top tree level (cached between events)
 
   __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
@@ -217,12 +221,21 @@ struct Runner {
       ml.senv = (uint8_t *)(ml.w2t + kHid * kLdH);
       ml.hst = (unsigned short *)(ml.senv + 64 * 32);
       ml.yb = (float *)(ml.hst + 16 * kLdH);
-      ml.ood = (int *)(ml.yb + 64);
-      ml.pb = (float *)(ml.ood + 40);
+      ml.pb = ml.yb + 64;
       ml.atile = (unsigned short *)(((uintptr_t)(ml.pb + 3 * kHid + 1) + 15) & ~(uintptr_t)15);
       stage_rows(ml.w1t, (const unsigned short *)(a.mlp_blob + mlay.w1t), kHid, k1, mlp_ld1(k1), gp.gl, G);
       stage_rows(ml.w2t, (const unsigned short *)(a.mlp_blob + mlay.w2t), kHid, kHid, kLdH, gp.gl, G);
-      if (gp.gl < 40) ml.ood[gp.gl] = hdr->ood_valid ? hdr->ood_max[gp.gl >> 3][gp.gl & 7] : 64;
+      seen = 0u;
+      for (int grp = 0; grp < 4; ++grp) {
+        uint32_t w = 0u;
+        for (int sp = 0; sp < 8; ++sp) {
+          const int b = (hdr->ood_valid && sp < Sm) ? min(hdr->ood_max[grp][sp], 15) : 15;
+          w |= (uint32_t)(b | 8) << (4 * sp);
+        }
+        oodw[grp] = w;
+      }
+      for (int sp = 0; sp < 8; ++sp)
+        if (!hdr->ood_valid || hdr->ood_max[4][sp] >= 1) seen |= 1u << sp;
       // The forward's biases and output weights in LDS, with a layout whose
       // offsets point there (the weight matrices are staged above).
       for (int x = gp.gl; x < kHid; x += G) {
@@ -379,10 +392,11 @@ struct Runner {
         // centre (the vacancy) is not part of N1(j) without i.
         const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, s.D1 + 8 * A, s.D2 + 8 * A);
         ea_pair = (float)(s.e0[A] + Real(0.5) * de);
-        ood = ml.ood[32 + A] < 1;  // moving species never seen in training
-        for (int sp = 0; sp < S; ++sp)
-          ood = ood || nib(c1i, sp) > ml.ood[sp] || nib(c2i, sp) > ml.ood[8 + sp] ||
-                nib(c1j, sp) > ml.ood[16 + sp] || nib(c2j, sp) > ml.ood[24 + sp];
+        // A count nibble c exceeds its bound b exactly when (b + 8) - c has
+        // its top bit clear (no borrow crosses nibbles: b + 8 - c >= 1).
+        const uint32_t hi = 0x88888888u;
+        ood = !((seen >> A) & 1u) || ((oodw[0] - c1i) & hi) != hi || ((oodw[1] - c2i) & hi) != hi ||
+              ((oodw[2] - c1j) & hi) != hi || ((oodw[3] - c2j) & hi) != hi;
       }
     }
     gsync();
