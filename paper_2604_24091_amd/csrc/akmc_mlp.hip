@@ -136,8 +136,10 @@ __global__ __launch_bounds__(256) void k_ood_fit(const uint8_t *__restrict__ env
 // ------------------------------------------------------ bulk inference
 
 constexpr int kFwdWaves = 8;
-// Per wavefront: 16 rows of 32 codes, then the 16-row activation tile.
-constexpr int kWaveBytes = 512 + 2 * 16 * kLdH;
+// Per wavefront: 16 rows of 32 codes, then one area for the one-hot input
+// tile and, once layer 1 has read it, the 16-row activation tile (one
+// wavefront's LDS operations take effect in program order).
+constexpr int kWaveBytes = 512 + kTileBytes;
 
 __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const unsigned char *__restrict__ blob,
                                                                 const uint8_t *__restrict__ env,
@@ -154,6 +156,7 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const unsigned c
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   uint8_t *senv = per_wave + wave * kWaveBytes;
   unsigned short *hst = (unsigned short *)(senv + 512);
+  unsigned short *atile = hst;
   const float *prm = (const float *)(blob + L.params);
   const float mu = hdr->mu, sigma = hdr->sigma;
   __syncthreads();
@@ -170,7 +173,8 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const unsigned c
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     unsigned short h1b[8][4], h2b[8][4];
     float gp1[8][4], gp2[8][4], y[4];
-    mlp_fwd16<false>(senv, w1t, w2t, hst, prm, L, S, k1, h1b, h2b, gp1, gp2, y);
+    onehot_tile(senv, atile, S, k1, l);
+    mlp_fwd16<false, true>((const uint8_t *)atile, w1t, w2t, hst, prm, L, S, k1, h1b, h2b, gp1, gp2, y);
     if ((l & 15) == 0) {
       const int q = l >> 4;
 #pragma unroll
@@ -239,6 +243,7 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_partial(TrainArg
   const int r = l & 15, q = l >> 4;
   uint8_t *senv = per_wave + wave * kWaveBytes;
   unsigned short *hst = (unsigned short *)(senv + 512);
+  unsigned short *atile = hst;
   const float *prm = (const float *)(ta.blob + L.params);
   const float mu = hdr->mu, sigma = hdr->sigma;
   const int gw = blockIdx.x * kTrainWaves + wave;  // wavefront index within the batch
@@ -267,7 +272,8 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_partial(TrainArg
 
   unsigned short h1b[8][4], h2b[8][4];
   float gp1[8][4], gp2[8][4], y[4];
-  mlp_fwd16<true>(senv, w1t, w2t, hst, prm, L, S, k1, h1b, h2b, gp1, gp2, y);
+  onehot_tile(senv, atile, S, k1, l);
+  mlp_fwd16<true, true>((const uint8_t *)atile, w1t, w2t, hst, prm, L, S, k1, h1b, h2b, gp1, gp2, y);
 
   float *part = ta.partial + (size_t)gw * (size_t)(np + 1);
   const float inv_b = 2.0f / (float)max(ta.rows, 1);   // d(mean loss)/dy over this step's rows

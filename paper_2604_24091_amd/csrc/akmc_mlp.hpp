@@ -22,14 +22,18 @@ constexpr int kHid = 128;
 // 16 consecutive rows at the same column, fall on different banks.
 constexpr int kPad = 8;
 constexpr int kLdH = kHid + kPad;
-__host__ __device__ inline int mlp_ld1(int k1) { return k1 + kPad; }
+__host__ __device__ constexpr int mlp_ld1(int k1) { return k1 + kPad; }
 constexpr int kSlots = 27;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__host__ __device__ inline int mlp_k1(int S) { return 32 * ((kSlots * S + 31) / 32); }
+__host__ __device__ constexpr int mlp_k1(int S) { return 32 * ((kSlots * S + 31) / 32); }
+// Bytes of a 16-row one-hot input tile at the largest species count (8); the
+// tile and the 16-row activation tile of the forward share this area.
+constexpr int kTileBytes = 2 * 16 * mlp_ld1(mlp_k1(8));
+static_assert(kTileBytes >= 2 * 16 * kLdH, "the activation tile fits the shared area");
 __host__ __device__ inline int mlp_nparams(int S) {
   const int k1 = mlp_k1(S);
   return k1 * kHid + kHid + kHid * kHid + kHid + kHid + 1;
