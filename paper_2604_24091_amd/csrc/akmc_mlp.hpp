@@ -84,10 +84,8 @@ __device__ __forceinline__ int div_s(int f, int magic) { return (f * magic) >> 1
 __host__ __device__ inline int s_magic(int S) { return (65536 + S - 1) / S; }
 
 __device__ __forceinline__ unsigned short f2bf(float f) {
-  // round to nearest even (finite values)
-  uint32_t u = __builtin_bit_cast(uint32_t, f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
+  // round to nearest even: the hardware conversion (v_cvt_pk_bf16_f32)
+  return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 __device__ __forceinline__ float bf2f(unsigned short h) {
   return __builtin_bit_cast(float, (uint32_t)h << 16);
