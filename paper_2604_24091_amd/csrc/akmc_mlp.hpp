@@ -109,17 +109,6 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
   return s + z * s * (1.0f - s) * (2.0f * c) * fmaf(3.0f * 0.044715f * z, z, 1.0f);
 }
 
-// Forward pass of 16 rows by one wavefront.
-//   env:   LDS, 16 rows x 32 bytes of species codes (27 used)
-//   w1t:   LDS, bf16 [128][k1 + kPad]   (output feature major, padded rows)
-//   w2t:   LDS, bf16 [128][kLdH]
-//   hst:   LDS, bf16 [16][128] staging of one activation tile
-//   prm:   binary32 parameter vector (biases, w3, b3)
-// Results per lane (C layout of the 16x16 matrix-core tiles: lane l holds
-// rows 4*(l/16)+i, column 16*c + l%16 of tile c):
-//   h1b[c][i], h2b[c][i]  bf16 activations; gp1/gp2 gelu'(z) (if GRAD);
-//   y[i] for rows 4*(l/16)+i (sum over all columns, identical in the 16
-//   lanes of a row group).
 // Copies rows x cols bf16 values (cols a multiple of 8) from a dense array
 // into LDS rows of pitch ld, 16 bytes per thread and step.
 __device__ __forceinline__ void stage_rows(unsigned short *dst, const unsigned short *src, int rows,
@@ -150,7 +139,18 @@ __device__ __forceinline__ void onehot_tile(const uint8_t *codes, unsigned short
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ATILE: env is the one-hot tile built by onehot_tile instead of codes.
+// Forward pass of 16 rows by one wavefront.
+//   env:   LDS, 16 rows x 32 bytes of species codes (27 used), or with
+//          ATILE the one-hot tile built by onehot_tile
+//   w1t:   LDS, bf16 [128][k1 + kPad]   (output feature major, padded rows)
+//   w2t:   LDS, bf16 [128][kLdH]
+//   hst:   LDS, bf16 [16][kLdH] staging of one activation tile
+//   prm:   binary32 parameter vector (biases, w3, b3)
+// Results per lane (C layout of the 16x16 matrix-core tiles: lane l holds
+// rows 4*(l/16)+i, column 16*c + l%16 of tile c):
+//   h1b[c][i], h2b[c][i]  bf16 activations; gp1/gp2 gelu'(z) (if GRAD);
+//   y[i] for rows 4*(l/16)+i (sum over all columns, identical in the 16
+//   lanes of a row group).
 template <bool GRAD, bool ATILE = false>
 __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned short *w1t,
                                           const unsigned short *w2t, unsigned short *hst,
