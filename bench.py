@@ -14,8 +14,9 @@ per site).  `value` is KMC events per second over the timed steps;
 The JSON line also carries:
   roofline      the bulk sweep kernel (k_rates_all) against HBM: algorithmic
                 bytes per launch (1 B occupancy read + 8 rates written per
-                site) over its mean launch time from HIP events on its
-                stream; traffic from the committed rocprofv3 counter
+                site) over its mean kernel time from HIP events that each
+                launch records at its kernel's start and end on its stream
+                (akmc_rates_timing); traffic from the committed rocprofv3 counter
                 summary when it still matches the kernel source;
   event_loop    per-event latency of the loop kernel;
   cpu_baseline  the CPU oracle (full rate recompute per event, binary64,
@@ -335,17 +336,21 @@ def main():
                   for _ in range(args.steps)]
         loops = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                  for _ in range(args.steps)]
+        for a, b in sweeps:  # create them; the sweep launches record them again
+            a.record(stream)
+            b.record(stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
             loops[k][0].record(stream)
             akmc.kmc_step(lat.h, args.events, None)
             loops[k][1].record(stream)
-            sweeps[k][0].record(stream)
+            # the sweep kernel's own start and end (hipExtLaunchKernel events)
+            akmc.rates_timing(lat.h, sweeps[k][0], sweeps[k][1])
             akmc.rates_eval(lat.h, akmc.RATES_ALL_SITES, None, 0, rates)
-            sweeps[k][1].record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        akmc.rates_timing(lat.h, None, None)
     wall = t1 - t0
     sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in sweeps]))
     loop_ms = float(np.mean([a.elapsed_time(b) for a, b in loops]))

@@ -163,6 +163,16 @@ akmc_status akmc_lattice_create(const akmc_params *p, const uint8_t *occ_host,
 akmc_status akmc_rates_eval(akmc_handle h, int32_t mode, const int32_t *d_sites,
                             int64_t n_sites, void *d_rates_out, void *d_ea_out);
 
+/* Kernel timing of the bulk evaluation, for benchmarks and profilers (the
+ * roofline of the AKMC_RATES_ALL_SITES kernel, Sec. III-B1's memory-bound
+ * rate enumeration): every later AKMC_RATES_ALL_SITES launch on h records
+ * start_event and stop_event (hipEvent_t, created by the caller, borrowed;
+ * either may be NULL) at the start and the end of its kernel's execution
+ * (hipExtLaunchKernel), so that hipEventElapsedTime gives the kernel's own
+ * duration without the stream's dispatch gaps.  NULL, NULL stops it.
+ * Errors: INVALID (NULL handle). */
+akmc_status akmc_rates_timing(akmc_handle h, void *start_event, void *stop_event);
+
 /* Performs exactly n_events residence-time events on the device with no
  * host round trip.  d_log: device array of n_events records, or NULL.
  * kmc_step(a) followed by kmc_step(b) gives the same state, bit for bit,

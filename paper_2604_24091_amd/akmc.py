@@ -91,6 +91,7 @@ def lib():
         L.akmc_workspace_bytes.argtypes = [P, C.c_int32, C.POINTER(sz)]
         L.akmc_lattice_create.argtypes = [P, vp, vp, vp, sz, vp, C.POINTER(vp)]
         L.akmc_rates_eval.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, vp]
+        L.akmc_rates_timing.argtypes = [vp, vp, vp]
         L.akmc_kmc_step.argtypes = [vp, C.c_int64, vp]
         L.akmc_state_read.argtypes = [vp, vp, vp, C.POINTER(Summary)]
         L.akmc_lattice_destroy.argtypes = [vp]
@@ -125,7 +126,7 @@ def lib():
         L.akmc_status_string.restype = C.c_char_p
         L.akmc_last_error.restype = C.c_char_p
         for name in ("akmc_workspace_bytes", "akmc_lattice_create", "akmc_rates_eval",
-                     "akmc_kmc_step", "akmc_state_read", "akmc_lattice_destroy",
+                     "akmc_rates_timing", "akmc_kmc_step", "akmc_state_read", "akmc_lattice_destroy",
                      "akmc_batch_workspace_bytes", "akmc_batch_create", "akmc_batch_set_schedule",
                      "akmc_batch_step", "akmc_batch_autotune", "akmc_batch_state_read",
                      "akmc_batch_destroy"):
@@ -219,6 +220,15 @@ def lattice_create(params: Params, occ_host: np.ndarray, ws, stream=None,
 def rates_eval(h: int, mode: int, sites, n_sites: int, rates_out, ea_out=None):
     _check(lib().akmc_rates_eval(h, int(mode), _ptr(sites), int(n_sites), _ptr(rates_out),
                                  _ptr(ea_out)), "rates_eval")
+
+
+def rates_timing(h: int, start=None, stop=None):
+    """Events (torch.cuda.Event, already recorded once so that they exist)
+    that every later ALL_SITES launch on h records at its kernel's start and
+    end; None, None stops it."""
+    def ev(e):
+        return None if e is None else C.c_void_p(e.cuda_event)
+    _check(lib().akmc_rates_timing(h, ev(start), ev(stop)), "rates_timing")
 
 
 def kmc_step(h: int, n_events: int, log=None):

@@ -214,6 +214,7 @@ struct akmc_lattice {
   double *d_scratch;
   uint8_t *d_occ;
   const unsigned char *mlp_blob = nullptr;
+  LaunchTiming timing;  // events recorded by ALL_SITES launches (akmc_rates_timing)
 };
 
 extern "C" {
@@ -305,12 +306,19 @@ akmc_status akmc_rates_eval(akmc_handle h, int32_t mode, const int32_t *d_sites,
           (reinterpret_cast<uintptr_t>(d_ea_out) & 15))
         return fail(AKMC_ERR_INVALID, "ALL_SITES outputs must be 16-byte aligned");
       e = launch_rates_all(h->d_desc, h->h_desc, h->d_occ, h->p.precision, d_rates_out, d_ea_out,
-                           h->stream);
+                           h->stream, &h->timing);
       break;
     default:
       return fail(AKMC_ERR_INVALID, "unknown rates_eval mode");
   }
   if (e != hipSuccess) return hip_fail(e, "rates_eval launch");
+  return AKMC_OK;
+}
+
+akmc_status akmc_rates_timing(akmc_handle h, void *start_event, void *stop_event) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  h->timing.start = (hipEvent_t)start_event;
+  h->timing.stop = (hipEvent_t)stop_event;
   return AKMC_OK;
 }
 

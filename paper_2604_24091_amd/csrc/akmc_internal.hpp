@@ -146,11 +146,20 @@ hipError_t launch_cluster_hist(const uint8_t *d_occ, int lx, int ly, int lz, int
                                int64_t max_size, int64_t *d_hist, int *d_parent, int *d_size,
                                hipStream_t st);
 
+// Events that a launch records at the start and the end of its kernel's
+// execution (hipExtLaunchKernel), for callers that time kernels; either
+// may be null.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+
 hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h_desc, const uint8_t *occ,
                               const int32_t *sites, int64_t n_sites, int precision,
-                              void *rates, void *ea, hipStream_t stream);
+                              void *rates, void *ea, hipStream_t stream,
+                              const LaunchTiming *tm = nullptr);
 hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h_desc, const uint8_t *occ,
-                            int precision, void *rates, void *ea, hipStream_t stream);
+                            int precision, void *rates, void *ea, hipStream_t stream,
+                            const LaunchTiming *tm = nullptr);
 
 // Surrogate (akmc_mlp.hip).
 hipError_t launch_env_encode(const LatDesc *d_desc, const uint8_t *occ, const int32_t *sites,

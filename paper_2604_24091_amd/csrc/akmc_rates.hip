@@ -17,6 +17,7 @@
 //    against the all-Fe environment keeps it near zero, so binary32 keeps
 //    its relative accuracy.  A target enters with its own species only.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "akmc_device.hpp"
@@ -524,24 +525,35 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
 
 // ------------------------------------------------------------ launchers
 
+// A launch that records the caller's timing events, if any, at its kernel's
+// start and end.
+template <class K, class... Args>
+static void launch_timed(K k, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                         const LaunchTiming *tm, Args... args) {
+  if (tm && (tm->start || tm->stop))
+    hipExtLaunchKernelGGL(k, grid, block, (uint32_t)lds, st, tm->start, tm->stop, 0u, args...);
+  else
+    hipLaunchKernelGGL(k, grid, block, lds, st, args...);
+}
+
 hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                               const int32_t *sites, int64_t n_sites, int precision, void *rates,
-                              void *ea, hipStream_t stream) {
+                              void *ea, hipStream_t stream, const LaunchTiming *tm) {
   if (n_sites <= 0) return hipSuccess;
   const int64_t nthreads = n_sites * 8;
   const unsigned blocks = (unsigned)((nthreads + 255) / 256);
   if (precision == AKMC_FP32)
-    hipLaunchKernelGGL((k_rates_sites<float>), dim3(blocks), dim3(256), 0, stream, d_desc, occ,
-                       sites, n_sites, (float *)rates, (float *)ea);
+    launch_timed(k_rates_sites<float>, dim3(blocks), dim3(256), 0, stream, tm, d_desc, occ, sites,
+                 n_sites, (float *)rates, (float *)ea);
   else
-    hipLaunchKernelGGL((k_rates_sites<double>), dim3(blocks), dim3(256), 0, stream, d_desc, occ,
-                       sites, n_sites, (double *)rates, (double *)ea);
+    launch_timed(k_rates_sites<double>, dim3(blocks), dim3(256), 0, stream, tm, d_desc, occ, sites,
+                 n_sites, (double *)rates, (double *)ea);
   return hipGetLastError();
 }
 
 template <int TX, int TY, int TZ, int S, class Real>
 static hipError_t launch_sweep(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
-                               void *rates, void *ea, hipStream_t stream) {
+                               void *rates, void *ea, hipStream_t stream, const LaunchTiming *tm) {
   using Sh = SweepShape<TX, TY, TZ>;
   const dim3 tiles((unsigned)((h.lx + TX - 1) / TX), (unsigned)((h.ly + TY - 1) / TY),
                    (unsigned)((h.lz + TZ - 1) / TZ));
@@ -551,44 +563,45 @@ static hipError_t launch_sweep(const LatDesc *d_desc, const LatDesc &h, const ui
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k, tiles, dim3(kSweepThreads), lds, stream, d_desc, occ, (Real *)rates,
-                     (Real *)ea);
+  launch_timed(k, tiles, dim3(kSweepThreads), lds, stream, tm, d_desc, occ, (Real *)rates, (Real *)ea);
   return hipGetLastError();
 }
 
 template <int S, class Real>
 static hipError_t launch_sweep_s(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
-                                 void *rates, void *ea, hipStream_t stream) {
+                                 void *rates, void *ea, hipStream_t stream, const LaunchTiming *tm) {
   // binary64 takes the narrower brick so that several workgroups share a CU
   if constexpr (sizeof(Real) == 8)
-    return launch_sweep<16, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream);
+    return launch_sweep<16, 4, 4, S, Real>(d_desc, h, occ, rates, ea, stream, tm);
   else
-    return launch_sweep<16, 4, 8, S, Real>(d_desc, h, occ, rates, ea, stream);
+    return launch_sweep<16, 4, 8, S, Real>(d_desc, h, occ, rates, ea, stream, tm);
 }
 
 template <class Real>
 static hipError_t launch_sweep_r(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
-                                 void *rates, void *ea, hipStream_t stream) {
+                                 void *rates, void *ea, hipStream_t stream, const LaunchTiming *tm) {
   switch (h.S) {
-    case 2: return launch_sweep_s<2, Real>(d_desc, h, occ, rates, ea, stream);
-    case 3: return launch_sweep_s<3, Real>(d_desc, h, occ, rates, ea, stream);
-    case 4: return launch_sweep_s<4, Real>(d_desc, h, occ, rates, ea, stream);
-    case 5: return launch_sweep_s<5, Real>(d_desc, h, occ, rates, ea, stream);
-    case 6: return launch_sweep_s<6, Real>(d_desc, h, occ, rates, ea, stream);
-    case 7: return launch_sweep_s<7, Real>(d_desc, h, occ, rates, ea, stream);
-    case 8: return launch_sweep_s<8, Real>(d_desc, h, occ, rates, ea, stream);
+    case 2: return launch_sweep_s<2, Real>(d_desc, h, occ, rates, ea, stream, tm);
+    case 3: return launch_sweep_s<3, Real>(d_desc, h, occ, rates, ea, stream, tm);
+    case 4: return launch_sweep_s<4, Real>(d_desc, h, occ, rates, ea, stream, tm);
+    case 5: return launch_sweep_s<5, Real>(d_desc, h, occ, rates, ea, stream, tm);
+    case 6: return launch_sweep_s<6, Real>(d_desc, h, occ, rates, ea, stream, tm);
+    case 7: return launch_sweep_s<7, Real>(d_desc, h, occ, rates, ea, stream, tm);
+    case 8: return launch_sweep_s<8, Real>(d_desc, h, occ, rates, ea, stream, tm);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
-                            int precision, void *rates, void *ea, hipStream_t stream) {
-  if (precision == AKMC_FP32) return launch_sweep_r<float>(d_desc, h, occ, rates, ea, stream);
+                            int precision, void *rates, void *ea, hipStream_t stream,
+                            const LaunchTiming *tm) {
+  if (precision == AKMC_FP32) return launch_sweep_r<float>(d_desc, h, occ, rates, ea, stream, tm);
   // The binary64 sweep's factors must stay inside the exponent range; tables
   // that could leave it take the per-candidate kernel over every site.
   if (!h.sweep_factor_ok)
-    return launch_rates_sites(d_desc, h, occ, nullptr, 2 * h.ncell, precision, rates, ea, stream);
-  return launch_sweep_r<double>(d_desc, h, occ, rates, ea, stream);
+    return launch_rates_sites(d_desc, h, occ, nullptr, 2 * h.ncell, precision, rates, ea, stream,
+                              tm);
+  return launch_sweep_r<double>(d_desc, h, occ, rates, ea, stream, tm);
 }
 
 }  // namespace akmc
