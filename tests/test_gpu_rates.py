@@ -173,3 +173,29 @@ def test_all_sites_fp64_wide_exponent_range(oracle_mod, scale):
     assert np.array_equal(r == 0, ~m)
     assert np.max(np.abs(r[m] - ro[m]) / ro[m]) <= 1e-12
     assert np.max(np.abs(e[m] - eo[m])) <= 1e-12
+
+
+def test_rates_timing_events_bracket_the_sweep_kernel():
+    """akmc_rates_timing: the ALL_SITES launch records the caller's events at
+    its kernel's start and end; clearing them leaves later launches alone."""
+    import torch
+    banner("rates timing events")
+    spec = W.random_lattice(np.random.default_rng(5), (32, 16, 16), 5, 20, solute_total=0.05)
+    stream = torch.cuda.Stream()
+    lat = akmc.Lattice(spec, precision=akmc.FP32, stream=stream)
+    out = torch.empty((spec.n_sites, 8), dtype=torch.float32, device="cuda")
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        a.record(stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        akmc.rates_timing(lat.h, a, b)
+        akmc.rates_eval(lat.h, akmc.RATES_ALL_SITES, None, 0, out)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        akmc.rates_timing(lat.h, None, None)
+        ref = lat.rates(akmc.RATES_ALL_SITES)
+        torch.cuda.synchronize()
+    lat.close()
+    assert 0.0 < ms < 1000.0
+    assert torch.equal(out, ref)
