@@ -230,14 +230,18 @@ akmc_status akmc_batch_workspace_bytes(int32_t n_rep, const akmc_params *p,
 /* p[n_rep] parameters (each replica's own lattice, temperature and Philox
  * key); occ_host[r] its occupancy; slot_sites_host NULL, or per replica a
  * slot list or NULL (as in lattice_create).  Same ownership rules as
- * lattice_create. */
+ * lattice_create.  The initial schedule serves each replica with 8 lanes,
+ * or with the fewest lanes whose groups fit in a workgroup's LDS. */
 akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p,
                               const uint8_t *const *occ_host,
                               const int32_t *const *slot_sites_host, void *d_ws,
                               size_t ws_bytes, void *hip_stream, akmc_batch *out);
 
 /* Sets the launch schedule (see akmc_batch_autotune).  Results do not
- * depend on the schedule. */
+ * depend on the schedule.  Errors: INVALID (field out of range),
+ * UNSUPPORTED (the (64 / group_lanes) * waves_per_block groups of a block,
+ * each holding the largest replica's rate tree, slot lists and footprint
+ * boxes, need more than the 160 KiB of LDS of a workgroup). */
 akmc_status akmc_batch_set_schedule(akmc_batch b, const akmc_schedule *s);
 
 /* Runs n_events events in every replica.  Asynchronous. */
@@ -245,7 +249,8 @@ akmc_status akmc_batch_step(akmc_batch b, int64_t n_events_per_replica);
 
 /* Times candidate schedules on the live batch (each trial advances every
  * replica by trial_events events; results do not depend on the schedule),
- * keeps the fastest and returns it.  Synchronises the stream. */
+ * keeps the fastest and returns it; schedules that do not fit in LDS (see
+ * akmc_batch_set_schedule) are skipped.  Synchronises the stream. */
 akmc_status akmc_batch_autotune(akmc_batch b, int64_t trial_events, akmc_schedule *chosen);
 
 /* State of replica r (synchronises the stream). */
@@ -324,7 +329,10 @@ akmc_status akmc_mlp_forward(const void *d_blob, int32_t n_species, const uint8_
  * evaluated on the matrix cores; candidates out of distribution (see
  * akmc_mlp_fit_ood) use the pair barrier and are counted in
  * akmc_summary.n_ood.  The blob is borrowed and must outlive the handle.
- * Synchronises the handle's stream. */
+ * Synchronises the handle's stream.  Errors: INVALID (pair-model handle,
+ * blob for another species count), UNSUPPORTED (the vacancies' rate tree
+ * and the staged weights need more than the 160 KiB of LDS of a workgroup,
+ * which happens only with 8 species and more than 504 vacancies). */
 akmc_status akmc_mlp_attach(akmc_handle h, const void *d_blob);
 
 /* Scratch bytes of training with this batch. */

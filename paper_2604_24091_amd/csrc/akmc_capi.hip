@@ -510,6 +510,12 @@ BatchLayout batch_layout(int n_rep, const akmc_params *p, const int32_t *n_vac) 
   return b;
 }
 
+// The loop keeps every group's tree, lists and boxes in LDS: a schedule is
+// usable only if (64 / lanes) * waves groups of the largest replica fit.
+bool schedule_fits(int nv_max, int group_lanes, int waves_per_block, int precision) {
+  return event_loop_lds_bytes(nv_max, group_lanes, waves_per_block, precision) <= kLdsBytes;
+}
+
 akmc_status check_schedule(const akmc_schedule *s) {
   if (!s) return fail(AKMC_ERR_INVALID, "schedule is NULL");
   if (s->group_lanes != 8 && s->group_lanes != 16 && s->group_lanes != 32 && s->group_lanes != 64)
@@ -628,7 +634,11 @@ akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p, const uint8_t
   b->d_slots = (int32_t *)(b->ws + lay.slots);
   b->d_scratch = (double *)(b->ws + lay.scratch);
   b->d_occ = b->ws + lay.occ;
-  b->sched = akmc_schedule{8, 1, 0, 0, 1 << 30};
+  // 8 lanes per replica, or the fewest lanes whose groups fit in LDS (64
+  // lanes always fit: one group per wavefront).
+  int g0 = 8;
+  while (g0 < 64 && !schedule_fits(b->nv_max, g0, 1, b->precision)) g0 *= 2;
+  b->sched = akmc_schedule{g0, 1, 0, 0, 1 << 30};
 
   std::vector<LatState> states(n_rep);
   std::vector<double> weight(n_rep);
@@ -679,6 +689,10 @@ akmc_status akmc_batch_set_schedule(akmc_batch b, const akmc_schedule *s) {
   if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
   akmc_status st = check_schedule(s);
   if (st != AKMC_OK) return st;
+  if (!schedule_fits(b->nv_max, s->group_lanes, s->waves_per_block, b->precision))
+    return fail(AKMC_ERR_UNSUPPORTED,
+                "schedule needs more than the 160 KiB of LDS of a workgroup: use more lanes per "
+                "replica or fewer waves per block");
   b->sched = *s;
   return AKMC_OK;
 }
@@ -710,6 +724,7 @@ akmc_status akmc_batch_autotune(akmc_batch b, int64_t trial_events, akmc_schedul
   float best_ms = 1e30f;
   for (int G : lanes)
     for (int W : waves) {
+      if (!schedule_fits(b->nv_max, G, W, b->precision)) continue;
       akmc_schedule s = keep;
       s.group_lanes = G;
       s.waves_per_block = W;
@@ -904,6 +919,10 @@ akmc_status akmc_mlp_attach(akmc_handle h, const void *d_blob) {
   HIP_TRY(hipMemcpy(&hd, d_blob, sizeof(hd), hipMemcpyDeviceToHost));
   if (hd.S != h->p.n_species || hd.k1 != mlp_k1(hd.S))
     return fail(AKMC_ERR_INVALID, "blob was built for a different species count");
+  if (event_loop_mlp_lds_bytes(std::max(h->nv, 1), hd.S) > kLdsBytes)
+    return fail(AKMC_ERR_UNSUPPORTED,
+                "the vacancies' rate tree and the network's weights exceed the 160 KiB of LDS of a "
+                "workgroup: use fewer vacancies or species");
   h->mlp_blob = (const unsigned char *)d_blob;
   return AKMC_OK;
 }

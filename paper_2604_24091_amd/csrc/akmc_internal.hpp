@@ -141,6 +141,10 @@ hipError_t launch_event_loop(const LoopArgs &a, int precision, int refresh_full,
 hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_species,
                                  hipStream_t stream);
 size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision);
+// LDS of the event loop with the learned barrier (one 64-lane group).
+size_t event_loop_mlp_lds_bytes(int nv_max, int n_species);
+// LDS a workgroup may hold on gfx950.
+constexpr size_t kLdsBytes = 160 * 1024;
 hipError_t launch_queue_reset(int32_t *queue, hipStream_t stream);
 hipError_t launch_cluster_hist(const uint8_t *d_occ, int lx, int ly, int lz, int species,
                                int64_t max_size, int64_t *d_hist, int *d_parent, int *d_size,

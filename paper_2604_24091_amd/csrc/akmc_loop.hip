@@ -888,6 +888,10 @@ size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, in
   return (size_t)L.bytes * (size_t)(64 / group_lanes) * (size_t)waves_per_block;
 }
 
+size_t event_loop_mlp_lds_bytes(int nv_max, int n_species) {
+  return (size_t)make_layout(nv_max, 64, 1).bytes + mlp_loop_lds_bytes(n_species);
+}
+
 template <int G, int W, bool FP32>
 static hipError_t launch_one(const LoopArgs &a, const Schedule &s, hipStream_t stream) {
   const GroupLayout L = make_layout(a.nv_max, G, FP32 ? 1 : 0);
@@ -935,7 +939,7 @@ hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_spec
   hipError_t e = launch_queue_reset(a.queue, stream);
   if (e != hipSuccess) return e;
   const GroupLayout L = make_layout(a.nv_max, 64, 1);
-  const size_t lds = (size_t)L.bytes + mlp_loop_lds_bytes(n_species);
+  const size_t lds = event_loop_mlp_lds_bytes(a.nv_max, n_species);
   auto kern = k_event_loop<64, 1, true, true>;
   e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

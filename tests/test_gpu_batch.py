@@ -97,3 +97,36 @@ def test_batch_fp32_equals_standalone():
     for r in (0, 9):
         occ, sl, s, _ = run_gpu(specs[r], 2000, log=False, precision=akmc.FP32)
         assert np.array_equal(res[r][0], occ) and res[r][2].digest == s.digest
+
+
+def test_batch_up_to_the_vacancy_limit_fits_lds():
+    """Replicas up to the vacancy limit (512): a schedule whose groups need
+    more LDS than a workgroup has is refused (UNSUPPORTED), the initial
+    schedule and the autotuner use only schedules that fit, and every
+    replica still ends where its standalone run ends."""
+    import torch
+    banner("batch up to the vacancy limit")
+    rng = np.random.default_rng(23)
+    specs = [W.random_lattice(rng, (12, 12, 12), 5, nv, solute_total=0.2)
+             for nv in (akmc.MAX_VACANCIES, 300, 40, 3)]
+    params = [akmc.make_params(s) for s in specs]
+    nv = [int(np.count_nonzero(s.occ == 4)) for s in specs]
+    ws = torch.empty(akmc.batch_workspace_bytes(params, nv), dtype=torch.uint8, device="cuda")
+    b = akmc.batch_create(params, [s.occ for s in specs], ws)
+    for lanes, waves in ((8, 1), (16, 1), (64, 4)):
+        with pytest.raises(akmc.AkmcError):
+            akmc.batch_set_schedule(b, akmc.Schedule(lanes, waves, 0, 0, 1000))
+    akmc.batch_step(b, 300)                     # initial schedule
+    chosen = akmc.batch_autotune(b, 100)
+    assert chosen.group_lanes >= 32
+    akmc.batch_step(b, 400)
+    outs = []
+    for r, s in enumerate(specs):
+        occ = np.empty(s.n_sites, np.uint8)
+        outs.append((occ, akmc.batch_state_read(b, r, occ)))
+    akmc.batch_destroy(b)
+    n = outs[0][1].n_events
+    assert all(o[1].n_events == n for o in outs) and n >= 1000
+    for r in range(len(specs)):
+        occ, _, s, _ = run_gpu(specs[r], n, log=False)
+        assert np.array_equal(outs[r][0], occ) and outs[r][1].digest == s.digest

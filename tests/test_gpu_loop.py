@@ -61,6 +61,16 @@ def test_random_alloys_fp64(oracle_mod, dims, S, nv, seed, n):
     _assert_same_trajectory(oracle_mod, spec, n)
 
 
+def test_max_vacancies_fp64(oracle_mod):
+    """The vacancy limit (512 = 8^3 slots: a full three-level rate tree),
+    15% of the sites vacant: many vacancy-vacancy masks and multi-slot
+    refresh passes; bit-exact against the oracle."""
+    banner("loop max vacancies fp64")
+    spec = W.random_lattice(np.random.default_rng(41), (12, 12, 12), 5, akmc.MAX_VACANCIES,
+                            solute_total=0.2)
+    _assert_same_trajectory(oracle_mod, spec, 1500)
+
+
 def test_rpv_524k_fp64(oracle_mod):
     """64^3 cells (524,288 sites), 10 vacancies, Fe-Cu-Ni-Mn, binary64."""
     banner("loop rpv_524k fp64 2e4")

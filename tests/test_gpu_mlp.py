@@ -205,17 +205,18 @@ def test_training_learns_the_pair_barrier(oracle_mod):
     assert np.max(np.abs(ref - pred[:2000].cpu().numpy())) <= 2e-3
 
 
-def test_mlp_loop_constant_network_equals_pair_model():
+@pytest.mark.parametrize("nv,n", [(25, 20000), (akmc.MAX_VACANCIES, 3000)])
+def test_mlp_loop_constant_network_equals_pair_model(nv, n):
     """Learned barrier inside the event loop, exactly checkable: a network
     whose output is the constant E0(Fe), with out-of-distribution bounds
     fitted on the all-Fe environment.  Every all-Fe candidate then gets the
     pair barrier's value from the network, every other candidate falls back
     to the pair barrier, so the trajectory must equal the binary32 pair
-    trajectory bit for bit, and the fallbacks are counted."""
+    trajectory bit for bit, and the fallbacks are counted.  At the vacancy
+    limit the tree and the staged weights fill most of the LDS."""
     import torch
-    banner("mlp loop constant network")
-    spec = W.random_lattice(np.random.default_rng(12), (14, 14, 14), S, 25, solute_total=0.03)
-    n = 20000
+    banner("mlp loop constant network nv=%d" % nv)
+    spec = W.random_lattice(np.random.default_rng(12), (14, 14, 14), S, nv, solute_total=0.03)
     ref = akmc.Lattice(spec, precision=akmc.FP32)
     buf_r = ref.step(n, log=True)
     blob = _blob(torch)
@@ -281,3 +282,26 @@ def test_mlp_loop_trained_network_runs_physically(oracle_mod):
     rmse = 1000 * float(torch.sqrt(torch.mean((pred[m] - ea_v[m]) ** 2)))
     print("in-loop state barrier rmse %.2f meV, n_ood %d" % (rmse, s.n_ood))
     assert rmse < 40.0
+
+
+def test_mlp_attach_refuses_what_does_not_fit_lds():
+    """8 species at the vacancy limit: the rate tree and the staged weights
+    exceed a workgroup's LDS, so attaching is refused (UNSUPPORTED) and a
+    step without weights is refused too; 504 vacancies fit."""
+    import torch
+    banner("mlp attach lds limit")
+    S8 = 8
+    blob = torch.empty(akmc.mlp_blob_bytes(S8), dtype=torch.uint8, device="cuda")
+    zero = np.zeros(akmc.mlp_param_count(S8), dtype=np.float32)
+    for nv, ok in ((akmc.MAX_VACANCIES, False), (504, True)):
+        spec = W.random_lattice(np.random.default_rng(19), (10, 10, 10), S8, nv, solute_total=0.2)
+        akmc.mlp_set_params(blob, S8, zero, float(np.float32(spec.e0[0])), 1.0)
+        lat = akmc.Lattice(spec, precision=akmc.FP32, barrier_model=akmc.BARRIER_MLP)
+        if ok:
+            akmc.mlp_attach(lat.h, blob)
+        else:
+            with pytest.raises(akmc.AkmcError):
+                akmc.mlp_attach(lat.h, blob)
+            with pytest.raises(akmc.AkmcError):
+                lat.step(10)
+        lat.close()

@@ -17,7 +17,9 @@ CASES = [((3, 3, 3), 3, 4, 1), ((5, 4, 6), 5, 12, 2), ((12, 12, 12), 5, 40, 3),
          ((40, 9, 6), 2, 20, 7), ((44, 7, 7), 5, 20, 8), ((41, 7, 6), 3, 10, 9),
          # staging paths of the sweep: 8-byte rows at the smallest edges that
          # allow them, with wraps on every axis; dword rows
-         ((24, 7, 11), 5, 10, 10), ((40, 12, 16), 4, 30, 11), ((28, 9, 13), 5, 15, 12)]
+         ((24, 7, 11), 5, 10, 10), ((40, 12, 16), 4, 30, 11), ((28, 9, 13), 5, 15, 12),
+         # the vacancy limit
+         ((12, 12, 12), 5, 512, 13)]
 
 
 def _compare(spec, oracle_mod, precision, mode):
