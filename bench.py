@@ -21,6 +21,8 @@ The JSON line also carries:
   event_loop    per-event latency of the loop kernel;
   cpu_baseline  the CPU oracle (full rate recompute per event, binary64,
                 one core) on a bounded sample of the same workload;
+  cpu_baseline_local  the oracle's local-refresh mode (classical CPU AKMC
+                locality, same trajectory) on a longer sample;
   forms         binary64 path, the batched replica ensemble (256 replicas
                 of 16^3..48^3 cells) and the learned-barrier form, each timed
                 separately outside the main timed region.
@@ -120,15 +122,21 @@ def write_traffic(fetch_dir, write_dir, tag):
     print(json.dumps(out))
 
 
-def cpu_baseline(spec, n_events):
+def cpu_baseline(spec, n_events, local=False):
+    """The oracle on one host thread.  local=False: the plain oracle (full
+    recompute of every rate before every event); local=True: its local
+    refresh mode, the classical CPU code's locality (same trajectory)."""
     from oracle import akmc_oracle as O
     o = O.Oracle(spec, precision=0)
     t0 = time.perf_counter()
-    done = o.run(n_events)
+    done = o.run(n_events, local=local)
     dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d events of the same 4.2M-site lattice, binary64, full rate "
-                      "recompute of all 1,600 candidates per event, one thread (%.1f s)" % (done, dt)}
+    how = ("local refresh (after each jump only the vacancies within 3 half-cells of the two "
+           "exchanged sites)" if local else "full rate recompute of all 1,600 candidates per event")
+    return {"value": done / dt, "unit": "events/s", "cores": 1,
+            "kind": "oracle-local-refresh" if local else "oracle",
+            "sample": "first %d events of the same 4.2M-site lattice, binary64, %s, one thread "
+                      "(%.1f s)" % (done, how, dt)}
 
 
 def bench_forms(args, torch, akmc, W, stream):
@@ -283,6 +291,8 @@ def main():
     ap.add_argument("--events", type=int, default=100_000, help="events per step")
     ap.add_argument("--batch-events", type=int, default=2_000, help="events per replica (batched form)")
     ap.add_argument("--cpu-events", type=int, default=30_000, help="oracle sample size (about 15 s)")
+    ap.add_argument("--cpu-local-events", type=int, default=200_000,
+                    help="sample of the oracle's local-refresh mode (about 8 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--fp64", action="store_true", help="time the binary64 path as the main line")
@@ -407,6 +417,7 @@ def main():
         line["forms"] = bench_forms(args, torch, akmc, W, stream)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_events)
+        line["cpu_baseline_local"] = cpu_baseline(spec, args.cpu_local_events, local=True)
     print(json.dumps(line), flush=True)
 
 

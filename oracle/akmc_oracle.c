@@ -10,7 +10,10 @@
  *   - Classical AKMC (Sec. III-B1): before every event, every migration
  *     direction of every vacancy is enumerated and its rate evaluated.
  *     This oracle does exactly that: a full recompute of all rates at every
- *     event, with no incremental bookkeeping.
+ *     event, with no incremental bookkeeping.  A second entry point
+ *     refreshes after each jump only the vacancies within reach of the two
+ *     exchanged sites (the locality that lets classical codes scale); it
+ *     gives the same trajectory and serves as the classical CPU baseline.
  *   - Rate of a candidate: the Arrhenius law of Eq. 8, r = nu exp(-Ea/kB T).
  *   - Feasibility mask (Eq. 1): a jump whose target site holds a vacancy is
  *     inadmissible and gets rate zero.
@@ -320,16 +323,40 @@ double orc_gamma_tot(const orc_params *p, const uint8_t *occ, const int32_t *slo
     return g;
 }
 
-/* Runs n_events events from (occ, slots, st).  Returns the number of events
- * done; -4 if the state is frozen before any event could be done (then
- * nothing changes).  log may be NULL. */
-int64_t orc_run(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
-                orc_state *st, int64_t n_events, orc_event *events) {
+/* Chebyshev distance between two sites in units of a/2 under the minimum
+ * image: with site (b, x, y, z) at 2x+b, 2y+b, 2z+b half-cells, each axis
+ * difference is taken modulo 2L and folded to at most L. */
+static int half_dist(const orc_params *p, int32_t s, int32_t t) {
+    int b1, x1, y1, z1, b2, x2, y2, z2;
+    orc_decode(p, s, &b1, &x1, &y1, &z1);
+    orc_decode(p, t, &b2, &x2, &y2, &z2);
+    const int d[3][3] = {{2 * x1 + b1, 2 * x2 + b2, 2 * p->lx},
+                         {2 * y1 + b1, 2 * y2 + b2, 2 * p->ly},
+                         {2 * z1 + b1, 2 * z2 + b2, 2 * p->lz}};
+    int m = 0;
+    for (int a = 0; a < 3; a++) {
+        int q = abs(d[a][0] - d[a][1]) % d[a][2];
+        if (d[a][2] - q < q) q = d[a][2] - q;
+        if (q > m) m = q;
+    }
+    return m;
+}
+
+/* The event loop of orc_run.  local = 0: every rate is recomputed before
+ * every event (the classical enumeration).  local = 1: all rates once, then
+ * after each jump only the slots whose vacancy lies within 3 half-cells of
+ * the two exchanged sites, the reach of a vacancy's 8 candidates (a rate
+ * reads sites up to 3 half-cells from its vacancy); every other rate is
+ * unchanged by the jump, so both modes give the same trajectory.  n_neg
+ * counts the candidates each mode evaluates. */
+static int64_t run_events(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
+                          orc_state *st, int64_t n_events, orc_event *events, int local) {
     int V = p->n_species - 1;
     double *rates = (double *)malloc(sizeof(double) * 8 * (size_t)(nv > 0 ? nv : 1));
     int64_t done = 0;
+    if (local) all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
     for (int64_t e = 0; e < n_events; e++) {
-        all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
+        if (!local) all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
         double u1, u2, g;
         orc_uniforms(p->seed, p->stream_id, st->n, &u1, &u2);
         int64_t c = orc_select(rates, 8 * (int64_t)nv, u1, &g);
@@ -361,10 +388,34 @@ int64_t orc_run(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
         st->t += dt;
         st->n += 1;
         done += 1;
+        if (local)
+            for (int32_t u = 0; u < nv; u++) {
+                if (half_dist(p, slots[u], i) > 3 && half_dist(p, slots[u], j) > 3) continue;
+                for (int kk = 0; kk < 8; kk++) {
+                    double ea, r;
+                    orc_candidate(p, occ, slots[u], kk, &ea, &r);
+                    rates[u * 8 + kk] = r;
+                    if (ea < 0.0) st->n_neg_barrier += 1;
+                }
+            }
     }
     st->gamma_tot = orc_gamma_tot(p, occ, slots, nv);
     free(rates);
     return done;
+}
+
+/* Runs n_events events from (occ, slots, st).  Returns the number of events
+ * done; -4 if the state is frozen before any event could be done (then
+ * nothing changes).  log may be NULL. */
+int64_t orc_run(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
+                orc_state *st, int64_t n_events, orc_event *events) {
+    return run_events(p, occ, slots, nv, st, n_events, events, 0);
+}
+
+/* orc_run with the local refresh described at run_events. */
+int64_t orc_run_local(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
+                      orc_state *st, int64_t n_events, orc_event *events) {
+    return run_events(p, occ, slots, nv, st, n_events, events, 1);
 }
 
 /* Replays a given event log on (occ, slots, st) in binary64 and reports how

@@ -84,6 +84,8 @@ def lib():
         L.orc_run.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState),
                               C.c_int64, C.c_void_p]
         L.orc_run.restype = C.c_int64
+        L.orc_run_local.argtypes = L.orc_run.argtypes
+        L.orc_run_local.restype = C.c_int64
         L.orc_follow.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState),
                                  C.c_int64, C.c_void_p, _f64p]
         L.orc_follow.restype = None
@@ -158,11 +160,14 @@ class Oracle:
         return lib().orc_gamma_tot(C.byref(self.p), self.occ, self.slots, self.slots.size)
 
     # events ----------------------------------------------------------------
-    def run(self, n_events: int, log: bool = False):
+    def run(self, n_events: int, log: bool = False, local: bool = False):
+        """n_events events; local=True refreshes after each jump only the
+        slots within reach of the exchanged sites (same trajectory)."""
         buf = np.zeros(max(n_events, 1), dtype=EVENT_DTYPE) if log else None
-        done = lib().orc_run(C.byref(self.p), self.occ, self.slots, self.slots.size,
-                             C.byref(self.state), int(n_events),
-                             buf.ctypes.data_as(C.c_void_p) if log else None)
+        fn = lib().orc_run_local if local else lib().orc_run
+        done = fn(C.byref(self.p), self.occ, self.slots, self.slots.size,
+                  C.byref(self.state), int(n_events),
+                  buf.ctypes.data_as(C.c_void_p) if log else None)
         if log:
             return done, buf[:max(done, 0)]
         return done

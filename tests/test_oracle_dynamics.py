@@ -197,3 +197,22 @@ def test_follow_accepts_own_log_and_rejects_a_wrong_choice(oracle_mod):
     bad[100]["dir"] = (bad[100]["dir"] + 1) % 8
     g = oracle_mod.Oracle(spec).follow(bad)
     assert g["mismatches"] == 1 or g["max_select_violation"] > 0.0
+
+
+@pytest.mark.parametrize("dims,S,nv,seed,n", [((3, 3, 3), 3, 3, 1, 500), ((6, 5, 7), 5, 20, 2, 1500),
+                                              ((10, 10, 10), 5, 130, 5, 800),
+                                              ((12, 12, 12), 5, 512, 41, 300)])
+def test_local_refresh_equals_full_recompute(oracle_mod, dims, S, nv, seed, n):
+    """A jump changes two sites and a rate reads sites at most 3 half-cells
+    from its vacancy: refreshing only the slots within that reach of either
+    site gives the full recompute's trajectory bit for bit (every logged
+    event with its Gamma_tot and dt, occupancy, slots, digest, time)."""
+    spec = W.random_lattice(np.random.default_rng(seed), dims, S, nv, solute_total=0.3)
+    a = oracle_mod.Oracle(spec)
+    da, la = a.run(n, log=True)
+    b = oracle_mod.Oracle(spec)
+    db, lb = b.run(n, log=True, local=True)
+    assert da == db == n
+    assert np.array_equal(la, lb)
+    assert np.array_equal(a.occ, b.occ) and np.array_equal(a.slots, b.slots)
+    assert a.state.digest == b.state.digest and a.state.t == b.state.t
