@@ -291,8 +291,8 @@ def main():
     ap.add_argument("--events", type=int, default=100_000, help="events per step")
     ap.add_argument("--batch-events", type=int, default=2_000, help="events per replica (batched form)")
     ap.add_argument("--cpu-events", type=int, default=30_000, help="oracle sample size (about 15 s)")
-    ap.add_argument("--cpu-local-events", type=int, default=200_000,
-                    help="sample of the oracle's local-refresh mode (about 8 s)")
+    ap.add_argument("--cpu-local-events", type=int, default=800_000,
+                    help="sample of the oracle's local-refresh mode (about 10 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
     ap.add_argument("--fp64", action="store_true", help="time the binary64 path as the main line")
