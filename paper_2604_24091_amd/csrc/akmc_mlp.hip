@@ -135,15 +135,25 @@ __global__ __launch_bounds__(256) void k_ood_fit(const uint8_t *__restrict__ env
 
 // ------------------------------------------------------ bulk inference
 
-constexpr int kFwdWaves = 8;
-// Per wavefront: 16 rows of 32 codes, then one area for the one-hot input
-// tile and, once layer 1 has read it, the 16-row activation tile (one
-// wavefront's LDS operations take effect in program order).
+// Per training wavefront: 16 rows of 32 codes, then one area for the
+// one-hot input tile and, once layer 1 has read it, the 16-row activation
+// tile (one wavefront's LDS operations take effect in program order).
 constexpr int kWaveBytes = 512 + kTileBytes;
 
-__global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const unsigned char *__restrict__ blob,
-                                                                const uint8_t *__restrict__ env,
-                                                                int64_t n, float *__restrict__ ea) {
+// Bulk inference: a block of up to kFwdWavesMax wavefronts shares the
+// weights staged in LDS; each wavefront owns one tile area sized for the
+// species count (fwd_wave_bytes), holding the one-hot input tile and, once
+// layer 1 has read it, the 16-row activation tile (one wavefront's LDS
+// operations take effect in program order).
+constexpr int kFwdWavesMax = 16;
+__host__ __device__ inline int fwd_wave_bytes(int k1) {
+  const int a = 2 * 16 * mlp_ld1(k1), h = 2 * 16 * kLdH;
+  return a > h ? a : h;
+}
+
+__global__ __launch_bounds__(64 * kFwdWavesMax) void k_mlp_forward(const unsigned char *__restrict__ blob,
+                                                                   const uint8_t *__restrict__ env,
+                                                                   int64_t n, float *__restrict__ ea) {
   extern __shared__ __align__(16) unsigned char mlp_lds[];
   const MlpHeader *hdr = (const MlpHeader *)blob;
   const int S = hdr->S, k1 = hdr->k1;
@@ -153,27 +163,18 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const unsigned c
   unsigned char *per_wave = (unsigned char *)(w2t + kHid * kLdH);
   stage_rows(w1t, (const unsigned short *)(blob + L.w1t), kHid, k1, mlp_ld1(k1), threadIdx.x, blockDim.x);
   stage_rows(w2t, (const unsigned short *)(blob + L.w2t), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  uint8_t *senv = per_wave + wave * kWaveBytes;
-  unsigned short *hst = (unsigned short *)(senv + 512);
-  unsigned short *atile = hst;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  unsigned short *atile = (unsigned short *)(per_wave + wave * fwd_wave_bytes(k1));
+  unsigned short *hst = atile;
   const float *prm = (const float *)(blob + L.params);
   const float mu = hdr->mu, sigma = hdr->sigma;
   __syncthreads();
   const int64_t tiles = (n + 15) / 16;
-  for (int64_t tile = (int64_t)blockIdx.x * kFwdWaves + wave; tile < tiles;
-       tile += (int64_t)gridDim.x * kFwdWaves) {
+  for (int64_t tile = (int64_t)blockIdx.x * nw + wave; tile < tiles; tile += (int64_t)gridDim.x * nw) {
     const int64_t row0 = tile * 16;
-    for (int e = l; e < 16 * 32; e += 64) {
-      const int r = e >> 5, s = e & 31;
-      senv[e] = (row0 + r < n && s < kSlots) ? env[(row0 + r) * kSlots + s] : 0;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     unsigned short h1b[8][4], h2b[8][4];
     float gp1[8][4], gp2[8][4], y[4];
-    onehot_tile(senv, atile, S, k1, l);
+    onehot_tile_rows(env, row0, n, atile, S, k1, l);
     mlp_fwd16<false, true>((const uint8_t *)atile, w1t, w2t, hst, prm, L, S, k1, h1b, h2b, gp1, gp2, y);
     if ((l & 15) == 0) {
       const int q = l >> 4;
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(256) void k_mlp_init(unsigned char *__restrict__ bl
 
 // ------------------------------------------------------------ launchers
 
-static size_t fwd_lds(int S) { return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + 2 * kHid * kLdH + kFwdWaves * kWaveBytes; }
+static size_t fwd_weight_bytes(int S) { return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + 2 * kHid * kLdH; }
 static size_t train_lds(int S) {
   return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + 2 * (size_t)2 * kHid * kLdH + kTrainWaves * kWaveBytes;
 }
@@ -506,12 +507,21 @@ hipError_t launch_ood_fit(unsigned char *blob, const uint8_t *env, int64_t n, in
 hipError_t launch_mlp_forward(const unsigned char *blob, int S, const uint8_t *env, int64_t n,
                               float *ea, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = fwd_lds(S);
+  // As many wavefronts per block as the LDS left by the weights holds, and
+  // a persistent grid of as many blocks as the CUs hold at once.
+  const size_t wbytes = fwd_weight_bytes(S), per = (size_t)fwd_wave_bytes(mlp_k1(S));
+  const int waves = (int)std::min<size_t>(kFwdWavesMax, (kLdsBytes - wbytes) / per);
+  const size_t lds = wbytes + (size_t)waves * per;
   hipError_t e = hipFuncSetAttribute((const void *)k_mlp_forward, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  int dev = 0, cus = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const int64_t per_cu = std::max<int64_t>(1, (int64_t)(kLdsBytes / lds));
   const int64_t tiles = (n + 15) / 16;
-  const unsigned blocks = (unsigned)std::min<int64_t>(2048, (tiles + kFwdWaves - 1) / kFwdWaves);
-  hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(64 * kFwdWaves), lds, stream, blob, env, n, ea);
+  const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + waves - 1) / waves, (int64_t)cus * per_cu));
+  hipLaunchKernelGGL(k_mlp_forward, dim3(blocks), dim3(64 * waves), lds, stream, blob, env, n, ea);
   return hipGetLastError();
 }
 

@@ -139,6 +139,27 @@ __device__ __forceinline__ void onehot_tile(const uint8_t *codes, unsigned short
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The same tile straight from n rows of kSlots codes in global memory, rows
+// row0 .. row0+15 (rows past n, and codes >= S, set no feature).
+__device__ __forceinline__ void onehot_tile_rows(const uint8_t *env, int64_t row0, int64_t n,
+                                                 unsigned short *atile, int S, int k1, int lane) {
+  const int ld = mlp_ld1(k1);
+  for (int u = lane; u < 16 * ld / 8; u += 64) *(uint4 *)(atile + 8 * u) = make_uint4(0u, 0u, 0u, 0u);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const int rows = n - row0 < 16 ? (int)(n - row0) : 16;
+  const uint8_t *src = env + row0 * kSlots;  // rows are contiguous: element u = row * kSlots + slot
+  for (int u = lane; u < rows * kSlots; u += 64) {
+    const int row = u / kSlots, slot = u - row * kSlots;
+    const int code = src[u];
+    if (code < S) atile[row * ld + slot * S + code] = 0x3F80;  // bf16 1.0
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Forward pass of 16 rows by one wavefront.
 //   env:   LDS, 16 rows x 32 bytes of species codes (27 used), or with
 //          ATILE the one-hot tile built by onehot_tile
