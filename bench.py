@@ -166,6 +166,7 @@ def bench_forms(args, torch, akmc, W, stream):
                      "sweep_gbs": spec.n_sites * 65 / sweep_s / 1e9}
     lat.close()
     del out
+    forms["fp32_vs_fp64"] = bench_fp32_error(torch, akmc, W, stream)
 
     # Batched voxel ensemble: 256 independent replicas, one persistent launch.
     reps = W.rpv_replicas()
@@ -196,6 +197,35 @@ def bench_forms(args, torch, akmc, W, stream):
     if args.surrogate_samples > 0:
         forms["surrogate"] = bench_surrogate(args, torch, akmc, W, stream)
     return forms
+
+
+def bench_fp32_error(torch, akmc, W, stream):
+    """Error of the binary32 path on the 4.2M-site lattice's initial state:
+    every site's 8 rates and barriers and the vacancies' total rate against
+    the binary64 path of the same library (which the parity tests hold
+    within 1e-12 of the oracle)."""
+    spec = W.rpv_4m()
+    res = {}
+    with torch.cuda.stream(stream):
+        out = {}
+        for prec in (akmc.FP32, akmc.FP64):
+            lat = akmc.Lattice(spec, precision=prec, stream=stream)
+            r, e = lat.rates(akmc.RATES_ALL_SITES, with_ea=True)
+            rv = lat.rates(akmc.RATES_VACANCIES)
+            torch.cuda.synchronize()
+            out[prec] = (r.double(), e.double(), float(rv.double().sum()))
+            lat.close()
+        r32, e32, g32 = out[akmc.FP32]
+        r64, e64, g64 = out[akmc.FP64]
+        m = r64 > 0
+        rel = ((r32 - r64).abs() / r64)[m]
+        res = {"candidates": int(m.sum()), "mask_equal": bool(torch.equal(r32 > 0, m)),
+               "max_rel_rate": float(rel.max()), "median_rel_rate": float(rel.median()),
+               "max_abs_ea_ev": float((e32 - e64).abs()[m].max()),
+               "gamma_tot_rel": abs(g32 - g64) / g64,
+               "reference": "binary64 path of the same library"}
+        del out, r32, e32, r64, e64, rel, m
+    return res
 
 
 MLP_FWD_FLOP = 2 * (160 * 128 + 128 * 128 + 128)     # per candidate, five species

@@ -427,13 +427,16 @@ int64_t orc_run_local(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t
  *   out[2] = max relative difference of the recorded dt
  *   out[3] = number of structural mismatches (wrong index, site, species,
  *            a masked candidate chosen)
+ *   out[4] = number of events whose recorded choice lies outside its
+ *            binary64 interval (a binary64 run with the same uniform would
+ *            have chosen another candidate)
  * The swaps recorded in the log are applied, so occ/slots end where the
  * logged trajectory ends. */
 void orc_follow(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
-                orc_state *st, int64_t n_events, const orc_event *events, double out[4]) {
+                orc_state *st, int64_t n_events, const orc_event *events, double out[5]) {
     int V = p->n_species - 1;
     double *rates = (double *)malloc(sizeof(double) * 8 * (size_t)(nv > 0 ? nv : 1));
-    out[0] = out[1] = out[2] = out[3] = 0.0;
+    out[0] = out[1] = out[2] = out[3] = out[4] = 0.0;
     for (int64_t e = 0; e < n_events; e++) {
         const orc_event *ev = &events[e];
         all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
@@ -453,6 +456,7 @@ void orc_follow(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
             if (before - target > viol) viol = before - target;
             if (target - after > viol) viol = target - after;
             if (viol / g > out[0]) out[0] = viol / g;
+            if (viol > 0.0) out[4] += 1.0;
             if (!(rates[c] > 0.0)) bad = 1;
             double dg = fabs(ev->gamma_tot - g) / g;
             if (dg > out[1]) out[1] = dg;

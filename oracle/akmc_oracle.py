@@ -174,12 +174,12 @@ class Oracle:
 
     def follow(self, log_records):
         recs = np.ascontiguousarray(log_records, dtype=EVENT_DTYPE)
-        out = np.zeros(4, dtype=np.float64)
+        out = np.zeros(5, dtype=np.float64)
         lib().orc_follow(C.byref(self.p), self.occ, self.slots, self.slots.size,
                          C.byref(self.state), recs.size,
                          recs.ctypes.data_as(C.c_void_p), out)
         return {"max_select_violation": out[0], "max_gamma_rel": out[1],
-                "max_dt_rel": out[2], "mismatches": int(out[3])}
+                "max_dt_rel": out[2], "mismatches": int(out[3]), "n_differ": int(out[4])}
 
     def cluster_hist(self, species: int = 1, max_size: int = 64, occ=None):
         occ = self.occ if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)

@@ -191,12 +191,12 @@ def test_follow_accepts_own_log_and_rejects_a_wrong_choice(oracle_mod):
     o = oracle_mod.Oracle(spec)
     _, log = o.run(500, log=True)
     f = oracle_mod.Oracle(spec).follow(log)
-    assert f["mismatches"] == 0 and f["max_select_violation"] == 0.0
+    assert f["mismatches"] == 0 and f["max_select_violation"] == 0.0 and f["n_differ"] == 0
     assert f["max_dt_rel"] == 0.0 and f["max_gamma_rel"] == 0.0
     bad = log.copy()
     bad[100]["dir"] = (bad[100]["dir"] + 1) % 8
     g = oracle_mod.Oracle(spec).follow(bad)
-    assert g["mismatches"] == 1 or g["max_select_violation"] > 0.0
+    assert g["mismatches"] == 1 or (g["max_select_violation"] > 0.0 and g["n_differ"] == 1)
 
 
 @pytest.mark.parametrize("dims,S,nv,seed,n", [((3, 3, 3), 3, 3, 1, 500), ((6, 5, 7), 5, 20, 2, 1500),
