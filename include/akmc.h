@@ -263,7 +263,7 @@ akmc_status akmc_batch_destroy(akmc_batch b);
 
 /* A small network predicts the barrier Ea of a candidate from the species in
  * the bonds the jump changes; the pair model stays as the fallback and as
- * the judge of its error.  It applies the paper's reformulation of per-atom
+ * the reference for its error.  It applies the paper's reformulation of per-atom
  * network evaluation as batched matrix products on matrix units with
  * reduced precision and fused layers (Sec. III-B1), trained with AdamW at
  * batch 256 (Sec. IV-C).
