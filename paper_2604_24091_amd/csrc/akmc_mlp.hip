@@ -161,8 +161,8 @@ __global__ __launch_bounds__(64 * kFwdWavesMax) void k_mlp_forward(const unsigne
   unsigned short *w1t = (unsigned short *)mlp_lds;
   unsigned short *w2t = w1t + kHid * mlp_ld1(k1);
   unsigned char *per_wave = (unsigned char *)(w2t + kHid * kLdH);
-  stage_rows(w1t, (const unsigned short *)(blob + L.w1t), kHid, k1, mlp_ld1(k1), threadIdx.x, blockDim.x);
-  stage_rows(w2t, (const unsigned short *)(blob + L.w2t), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
+  stage_rows8(w1t, (const unsigned short *)(blob + L.w1t), kHid, k1, mlp_ld1(k1), threadIdx.x, blockDim.x);
+  stage_rows8(w2t, (const unsigned short *)(blob + L.w2t), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
   unsigned short *atile = (unsigned short *)(per_wave + wave * fwd_wave_bytes(k1));
   unsigned short *hst = atile;
@@ -237,9 +237,9 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_partial(TrainArg
   unsigned short *w2t = w1t + kHid * mlp_ld1(k1);
   unsigned short *w2r = w2t + kHid * kLdH;
   unsigned char *per_wave = (unsigned char *)(w2r + kHid * kLdH);
-  stage_rows(w1t, (const unsigned short *)(ta.blob + L.w1t), kHid, k1, mlp_ld1(k1), threadIdx.x, blockDim.x);
-  stage_rows(w2t, (const unsigned short *)(ta.blob + L.w2t), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
-  stage_rows(w2r, (const unsigned short *)(ta.blob + L.w2r), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
+  stage_rows8(w1t, (const unsigned short *)(ta.blob + L.w1t), kHid, k1, mlp_ld1(k1), threadIdx.x, blockDim.x);
+  stage_rows8(w2t, (const unsigned short *)(ta.blob + L.w2t), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
+  stage_rows8(w2r, (const unsigned short *)(ta.blob + L.w2r), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int r = l & 15, q = l >> 4;
   uint8_t *senv = per_wave + wave * kWaveBytes;

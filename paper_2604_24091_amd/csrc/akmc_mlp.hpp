@@ -120,6 +120,32 @@ __device__ __forceinline__ void stage_rows(unsigned short *dst, const unsigned s
   }
 }
 
+// The same copy with eight loads in flight per thread before their stores,
+// for kernels that stage the weights once per block before any other work
+// (the registers are free then).
+__device__ __forceinline__ void stage_rows8(unsigned short *dst, const unsigned short *src, int rows,
+                                            int cols, int ld, int tid, int nthreads) {
+  const int per_row = cols / 8, total = rows * per_row;
+  int u = tid;
+  for (; u + 7 * nthreads < total; u += 8 * nthreads) {
+    uint4 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int w = u + k * nthreads, r = w / per_row, c8 = w - r * per_row;
+      v[k] = *(const uint4 *)(src + r * cols + 8 * c8);
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int w = u + k * nthreads, r = w / per_row, c8 = w - r * per_row;
+      *(uint4 *)(dst + r * ld + 8 * c8) = v[k];
+    }
+  }
+  for (; u < total; u += nthreads) {
+    const int r = u / per_row, c8 = u - r * per_row;
+    *(uint4 *)(dst + r * ld + 8 * c8) = *(const uint4 *)(src + r * cols + 8 * c8);
+  }
+}
+
 // One-hot input tile of 16 rows (bf16, pitch mlp_ld1(k1)) from 16 rows of
 // 32 species codes (the first kSlots used): the wavefront clears the tile,
 // then sets feature slot*S + code of every (row, slot).
