@@ -84,6 +84,35 @@ def test_rpv_4m_fp64(oracle_mod):
     _assert_same_trajectory(oracle_mod, W.rpv_4m(), 3_000)
 
 
+def test_rpv_4m_production_run_with_cluster_histograms(oracle_mod):
+    """The 4.2M-site workload as a production run: 10^7 binary32 events in
+    steps of 10^6, the Cu cluster-size histogram after every step equal to
+    the oracle's on the same occupancy, species counts conserved, time and
+    event count advancing, the lattice never frozen."""
+    import torch
+    banner("loop rpv_4m production 1e7 events")
+    spec = W.rpv_4m()
+    lat = akmc.Lattice(spec, precision=akmc.FP32)
+    counts0 = np.bincount(spec.occ, minlength=spec.n_species)
+    t_prev = 0.0
+    orc = oracle_mod.Oracle(spec)
+    try:
+        for c in range(10):
+            lat.step(1_000_000)
+            hist = lat.clusters(1, 256)
+            torch.cuda.synchronize()
+            occ, _, s = lat.read()
+            assert s.n_events == (c + 1) * 1_000_000 and s.frozen == 0 and s.t > t_prev
+            t_prev = s.t
+            assert np.array_equal(np.bincount(occ, minlength=spec.n_species), counts0)
+            _, ref = orc.cluster_hist(1, 256, occ)
+            assert np.array_equal(hist.cpu().numpy(), ref)
+            print("[gpu-case] after %d events: t = %.4e s, largest Cu cluster %d" %
+                  (s.n_events, s.t, int(np.flatnonzero(ref)[-1])), flush=True)
+    finally:
+        lat.close()
+
+
 def test_local_refresh_equals_full_refresh():
     banner("loop local vs full")
     spec = W.random_lattice(np.random.default_rng(21), (7, 7, 7), 5, 50, solute_total=0.2)
