@@ -130,3 +130,36 @@ def test_batch_up_to_the_vacancy_limit_fits_lds():
     for r in range(len(specs)):
         occ, _, s, _ = run_gpu(specs[r], n, log=False)
         assert np.array_equal(outs[r][0], occ) and outs[r][1].digest == s.digest
+
+
+def test_replica_ensemble_production_run():
+    """The 256-replica ensemble (16^3..48^3 cells, 1-20 vacancies, 523-593 K)
+    as a production run: 10^5 binary32 events per replica under the
+    autotuned schedule with graph replay; every replica conserves its
+    species and ran every event, and three replicas (the first, a middle
+    and the last in creation order) end bit for bit where their standalone
+    runs end."""
+    import torch
+    banner("batch ensemble production 1e5 events per replica")
+    specs = W.rpv_replicas()
+    params = [akmc.make_params(s, precision=akmc.FP32) for s in specs]
+    nv = [int(np.count_nonzero(s.occ == 4)) for s in specs]
+    ws = torch.empty(akmc.batch_workspace_bytes(params, nv), dtype=torch.uint8, device="cuda")
+    b = akmc.batch_create(params, [s.occ for s in specs], ws)
+    chosen = akmc.batch_autotune(b, 100)
+    akmc.batch_set_schedule(b, akmc.Schedule(chosen.group_lanes, chosen.waves_per_block, chosen.blocks,
+                                             1, 20_000))
+    akmc.batch_step(b, 100_000)
+    outs = []
+    for r, s in enumerate(specs):
+        occ = np.empty(s.n_sites, np.uint8)
+        summ = akmc.batch_state_read(b, r, occ)
+        outs.append((occ, summ))
+        assert summ.frozen == 0
+        assert np.array_equal(np.bincount(occ, minlength=5), np.bincount(s.occ, minlength=5))
+    akmc.batch_destroy(b)
+    n = outs[0][1].n_events
+    assert n == 100_000 + 8 * 100 and all(o[1].n_events == n for o in outs)
+    for r in (0, 128, 255):
+        occ, _, s, _ = run_gpu(specs[r], n, log=False, precision=akmc.FP32)
+        assert np.array_equal(outs[r][0], occ) and outs[r][1].digest == s.digest and outs[r][1].t == s.t
