@@ -122,6 +122,19 @@ def write_traffic(fetch_dir, write_dir, tag):
     print(json.dumps(out))
 
 
+def host_cpu():
+    """Model name of the host CPU (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(spec, n_events, local=False):
     """The oracle on one host thread.  local=False: the plain oracle (full
     recompute of every rate before every event); local=True: its local
@@ -134,6 +147,7 @@ def cpu_baseline(spec, n_events, local=False):
     how = ("local refresh (after each jump only the vacancies within 3 half-cells of the two "
            "exchanged sites)" if local else "full rate recompute of all 1,600 candidates per event")
     return {"value": done / dt, "unit": "events/s", "cores": 1,
+            "host_cpu": host_cpu(), "host_threads": os.cpu_count(),
             "kind": "oracle-local-refresh" if local else "oracle",
             "sample": "first %d events of the same 4.2M-site lattice, binary64, %s, one thread "
                       "(%.1f s)" % (done, how, dt)}
