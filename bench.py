@@ -406,7 +406,8 @@ def main():
         t1 = time.perf_counter()
         akmc.rates_timing(lat.h, None, None)
     wall = t1 - t0
-    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in sweeps]))
+    sweep_each = [a.elapsed_time(b) for a, b in sweeps]
+    sweep_ms = float(np.mean(sweep_each))
     loop_ms = float(np.mean([a.elapsed_time(b) for a, b in loops]))
     occ, slots, summ = lat.read()
     assert summ.n_events == args.events * (args.steps + args.warmup)
@@ -444,7 +445,8 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes,
-                     "launch_ms": sweep_ms},
+                     "launch_ms": sweep_ms,
+                     "launch_ms_each": [round(float(x), 5) for x in sweep_each]},
         "event_loop": {"kernel": "k_event_loop (one 64-lane group, persistent)",
                        "events_per_s": args.events / (loop_ms * 1e-3),
                        "us_per_event": loop_ms * 1e3 / args.events,
