@@ -69,3 +69,28 @@ def test_create_rejects_null_and_bad_codes_without_gpu():
 def test_struct_sizes_match_header():
     assert C.sizeof(akmc.Event) == 40
     assert C.sizeof(akmc.Params) == 4 * 4 + 8 * (64 + 64 + 8) + 8 * 3 + 8 * 2 + 8 * 3 + 4 * 4
+
+
+def test_null_handles_are_rejected_without_gpu():
+    """Every entry point that takes a lattice or batch handle checks it
+    first: NULL gives ERR_INVALID and touches no device."""
+    L = akmc.lib()
+    calls = [
+        lambda: L.akmc_rates_eval(None, 0, None, 0, None, None),
+        lambda: L.akmc_rates_timing(None, None, None),
+        lambda: L.akmc_kmc_step(None, 1, None),
+        lambda: L.akmc_state_read(None, None, None, None),
+        lambda: L.akmc_cluster_scratch_bytes(None, None),
+        lambda: L.akmc_cluster_hist(None, 1, 8, None, None, 0),
+        lambda: L.akmc_lattice_destroy(None),
+        lambda: L.akmc_env_encode(None, 0, None, 0, None, None),
+        lambda: L.akmc_mlp_attach(None, None),
+        lambda: L.akmc_batch_set_schedule(None, None),
+        lambda: L.akmc_batch_step(None, 1),
+        lambda: L.akmc_batch_autotune(None, 1, None),
+        lambda: L.akmc_batch_state_read(None, 0, None, None, None),
+        lambda: L.akmc_batch_destroy(None),
+    ]
+    for call in calls:
+        assert call() == akmc.ERR_INVALID
+        assert akmc.last_error()
