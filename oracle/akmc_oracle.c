@@ -49,11 +49,11 @@
  *     (n:int64, from:int32, to:int32) per event.
  *
  * Precision: fp64 throughout by default.  A second mode computes energy
- * change, barrier and rate in binary32 (fmaf chain; rate nu * 2^(Ea * c)
- * with c = -log2(e) / kT by one binary32 division, exp2f) and widens the
- * rate to binary64 before any sum; it exists so that
- * the oracle takes selection decisions in the same precision as a binary32
- * rate kernel.
+ * change, barrier and rate in binary32 (fmaf chain on the binary32 tables,
+ * Ea = E0 + dE/2, x = -(Ea / kT) by one binary32 division, rate
+ * nu * expf(x): the Arrhenius law of Eq. 8 written out in binary32) and
+ * widens the rate to binary64 before any sum, so that the oracle takes
+ * selection decisions in the same precision as a binary32 rate kernel.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math).
  */
@@ -94,7 +94,7 @@ typedef struct {
     double t;                    /* physical time, s */
     uint64_t digest;
     double gamma_tot;            /* total rate of the current state */
-    int64_t n_neg_barrier;       /* evaluated candidates with Ea < 0 */
+    int64_t n_neg_evaluated;     /* evaluations (every event's, in full-recompute mode) with Ea < 0 */
 } orc_state;
 
 /* ---------------------------------------------------------------- lattice */
@@ -185,13 +185,16 @@ double orc_delta_e(const orc_params *p, const uint8_t *occ, int32_t i, int k) {
     return acc;
 }
 
-/* Barrier and rate of one candidate.  Masked: Ea = +inf, rate = +0. */
-void orc_candidate(const orc_params *p, const uint8_t *occ, int32_t i, int k,
-                   double *ea_out, double *rate_out) {
+/* Barrier, energy change and rate of one candidate, in the precision of
+ * p->precision (widened to binary64).  Masked: Ea = +inf, dE = NaN,
+ * rate = +0. */
+static void candidate(const orc_params *p, const uint8_t *occ, int32_t i, int k,
+                      double *ea_out, double *de_out, double *rate_out) {
     int S = p->n_species, dn1[8], dn2[8];
     int A = counts(p, occ, i, k, dn1, dn2);
     if (A == S - 1) {
         *ea_out = INFINITY;
+        *de_out = NAN;
         *rate_out = 0.0;
         return;
     }
@@ -203,6 +206,7 @@ void orc_candidate(const orc_params *p, const uint8_t *occ, int32_t i, int k,
         double kt = p->kb * p->temperature;
         double x = -(ea / kt);
         *ea_out = ea;
+        *de_out = acc;
         *rate_out = p->nu * exp(x);
     } else {
         float acc = 0.0f;
@@ -210,11 +214,36 @@ void orc_candidate(const orc_params *p, const uint8_t *occ, int32_t i, int k,
         for (int s = 0; s < S; s++) acc = fmaf((float)dn2[s], (float)dtab(p->eps2, S, A, s), acc);
         float ea = (float)p->e0[A] + 0.5f * acc;
         float kt = (float)(p->kb * p->temperature);
-        float c = -1.44269504088896341f / kt;
-        float r = (float)p->nu * exp2f(ea * c);
+        float x = -(ea / kt);
+        float r = (float)p->nu * expf(x);
         *ea_out = (double)ea;
+        *de_out = (double)acc;
         *rate_out = (double)r;
     }
+}
+
+/* Barrier and rate of one candidate.  Masked: Ea = +inf, rate = +0. */
+void orc_candidate(const orc_params *p, const uint8_t *occ, int32_t i, int k,
+                   double *ea_out, double *rate_out) {
+    double de;
+    candidate(p, occ, i, k, ea_out, &de, rate_out);
+}
+
+/* Counts over the current candidates of the slots (admissible jumps only):
+ * out[0] those with Ea < 0, out[1] those with Ea < dE, i.e. whose reverse
+ * jump would have a negative barrier Ea - dE (both compared in the
+ * precision of p->precision). */
+void orc_barrier_counts(const orc_params *p, const uint8_t *occ, const int32_t *slots,
+                        int32_t nv, int64_t out[2]) {
+    out[0] = out[1] = 0;
+    for (int32_t v = 0; v < nv; v++)
+        for (int k = 0; k < 8; k++) {
+            double ea, de, r;
+            candidate(p, occ, slots[v], k, &ea, &de, &r);
+            if (!(r > 0.0) && isinf(ea)) continue;
+            if (ea < 0.0) out[0] += 1;
+            if (ea < de) out[1] += 1;
+        }
 }
 
 /* rates[n][8], ea[n][8] for a vacancy placed at each listed site. */
@@ -354,9 +383,9 @@ static int64_t run_events(const orc_params *p, uint8_t *occ, int32_t *slots, int
     int V = p->n_species - 1;
     double *rates = (double *)malloc(sizeof(double) * 8 * (size_t)(nv > 0 ? nv : 1));
     int64_t done = 0;
-    if (local) all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
+    if (local) all_rates(p, occ, slots, nv, rates, &st->n_neg_evaluated);
     for (int64_t e = 0; e < n_events; e++) {
-        if (!local) all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
+        if (!local) all_rates(p, occ, slots, nv, rates, &st->n_neg_evaluated);
         double u1, u2, g;
         orc_uniforms(p->seed, p->stream_id, st->n, &u1, &u2);
         int64_t c = orc_select(rates, 8 * (int64_t)nv, u1, &g);
@@ -395,7 +424,7 @@ static int64_t run_events(const orc_params *p, uint8_t *occ, int32_t *slots, int
                     double ea, r;
                     orc_candidate(p, occ, slots[u], kk, &ea, &r);
                     rates[u * 8 + kk] = r;
-                    if (ea < 0.0) st->n_neg_barrier += 1;
+                    if (ea < 0.0) st->n_neg_evaluated += 1;
                 }
             }
     }
@@ -439,7 +468,7 @@ void orc_follow(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
     out[0] = out[1] = out[2] = out[3] = out[4] = 0.0;
     for (int64_t e = 0; e < n_events; e++) {
         const orc_event *ev = &events[e];
-        all_rates(p, occ, slots, nv, rates, &st->n_neg_barrier);
+        all_rates(p, occ, slots, nv, rates, &st->n_neg_evaluated);
         double u1, u2;
         orc_uniforms(p->seed, p->stream_id, st->n, &u1, &u2);
         double g = 0.0;
@@ -542,4 +571,12 @@ void orc_encode_env(const orc_params *p, const uint8_t *occ, int32_t i, int k,
         out[21 + m] = occ[orc_nbr2(p, j, flipped ? (m ^ 1) : m)];
     }
     for (int d = 1; d < 8; d++) out[13 + d] = occ[orc_nbr1(p, j, d ^ flip)];
+}
+
+/* The 27 slot codes of all 8 candidates of every listed site:
+ * out[n][8][27]. */
+void orc_encode_env_sites(const orc_params *p, const uint8_t *occ, const int32_t *sites,
+                          int64_t n, uint8_t *out) {
+    for (int64_t a = 0; a < n; a++)
+        for (int k = 0; k < 8; k++) orc_encode_env(p, occ, sites[a], k, out + (a * 8 + k) * 27);
 }

@@ -34,7 +34,7 @@ class OrcEvent(C.Structure):
 
 class OrcState(C.Structure):
     _fields_ = [("n", C.c_int64), ("t", C.c_double), ("digest", C.c_uint64),
-                ("gamma_tot", C.c_double), ("n_neg_barrier", C.c_int64)]
+                ("gamma_tot", C.c_double), ("n_neg_evaluated", C.c_int64)]
 
 
 EVENT_DTYPE = np.dtype([("n", "<i8"), ("slot", "<i4"), ("from_site", "<i4"),
@@ -93,6 +93,10 @@ def lib():
         L.orc_cluster_hist.restype = C.c_int64
         L.orc_encode_env.argtypes = [P, _u8p, C.c_int32, C.c_int, _u8p]
         L.orc_encode_env.restype = None
+        L.orc_encode_env_sites.argtypes = [P, _u8p, _i32p, C.c_int64, _u8p]
+        L.orc_encode_env_sites.restype = None
+        L.orc_barrier_counts.argtypes = [P, _u8p, _i32p, C.c_int32, _i64p]
+        L.orc_barrier_counts.restype = None
         _lib = L
     return _lib
 
@@ -192,6 +196,21 @@ class Oracle:
         out = np.zeros(27, dtype=np.uint8)
         lib().orc_encode_env(C.byref(self.p), occ, int(i), int(k), out)
         return out
+
+    def encode_env_sites(self, sites, occ=None):
+        """Slot codes of the 8 candidates of every listed site: [n][8][27]."""
+        occ = self.occ if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
+        sites = np.ascontiguousarray(sites, dtype=np.int32)
+        out = np.zeros((sites.size, 8, 27), dtype=np.uint8)
+        lib().orc_encode_env_sites(C.byref(self.p), occ, sites, sites.size, out)
+        return out
+
+    def barrier_counts(self):
+        """(candidates with Ea < 0, candidates with Ea < dE) of the current
+        slots, admissible jumps only."""
+        out = np.zeros(2, dtype=np.int64)
+        lib().orc_barrier_counts(C.byref(self.p), self.occ, self.slots, self.slots.size, out)
+        return int(out[0]), int(out[1])
 
 
 def philox(counter, key):

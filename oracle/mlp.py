@@ -24,6 +24,13 @@ Definition (a reading; the paper gives no barrier network):
 bf16=True rounds x W-inputs and hidden activations to bfloat16 where the
 GPU kernels store them in bfloat16 (weights, h1, h2); accumulation stays
 binary64.
+
+Out of distribution (a reading; the paper's policy masks inadmissible
+moves but states no rule for unfamiliar environments): a candidate whose
+moving species never moved in the training rows, or whose count of some
+species in one of the four bond groups (N1(i) without j, N2(i), N1(j)
+without i, N2(j)) exceeds the largest count of that species in that group
+over the training rows, takes the pair-model barrier instead.
 """
 from __future__ import annotations
 
@@ -129,3 +136,44 @@ def adamw_step(p, g, state, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0
         vhat = v / (1.0 - beta2 ** t)
         p[k] = p[k] - lr * mhat / (np.sqrt(vhat) + eps)
     return p
+
+
+GROUPS = ((1, 8), (8, 14), (14, 21), (21, 27))   # slot ranges of the four bond groups
+
+
+def group_counts(env, S: int) -> np.ndarray:
+    """[n][4][S] per-species counts of the four bond groups."""
+    env = np.asarray(env).reshape(-1, N_SLOTS)
+    return np.stack([np.stack([(env[:, a:b] == s).sum(1) for s in range(S)], 1)
+                     for a, b in GROUPS], 1)
+
+
+def ood_bounds(train_env, S: int) -> dict:
+    """The training set's largest group counts and its moving species
+    (rows whose slot 0 is the vacancy code are not training rows)."""
+    tr = np.asarray(train_env).reshape(-1, N_SLOTS)
+    tr = tr[tr[:, 0] != S - 1]
+    return {"max": group_counts(tr, S).max(0), "seen": np.unique(tr[:, 0])}
+
+
+def in_distribution(bounds: dict, env, S: int) -> np.ndarray:
+    env = np.asarray(env).reshape(-1, N_SLOTS)
+    return np.isin(env[:, 0], bounds["seen"]) & \
+        np.all(group_counts(env, S) <= bounds["max"][None], axis=(1, 2))
+
+
+def barrier_model(p, bounds: dict, oracle, S: int, bf16_act: bool = True):
+    """Barriers of the learned model with its pair-model fallback, as a
+    function (occ, slots) -> [nv][8] (binary64; +inf for an inadmissible
+    jump).  oracle: an akmc_oracle.Oracle of the same lattice (pair barriers
+    and slot codes)."""
+    def fn(occ, slots):
+        _, ea_pair = oracle.rates_sites(slots, occ)
+        env = oracle.encode_env_sites(slots, occ).reshape(-1, N_SLOTS)
+        ea = ea_pair.reshape(-1).copy()
+        use = np.isfinite(ea) & in_distribution(bounds, env, S)
+        if use.any():
+            ea[use] = predict_ea(p, env[use], S, bf16_act)
+        return ea.reshape(-1, 8)
+    return fn
+

@@ -149,3 +149,68 @@ def test_pair_barrier_is_representable_exactly_by_the_features():
         X = np.hstack([M.one_hot(envs[m], 5), np.ones((m.sum(), 1))])
         coef, *_ = np.linalg.lstsq(X, eas[m], rcond=None)
         assert np.max(np.abs(X @ coef - eas[m])) < 1e-10
+
+
+def test_ood_rule_and_learned_barrier_model():
+    """The learned barrier model: inadmissible jumps stay +inf, candidates
+    whose moving species or any bond-group count lies outside the training
+    rows take the pair barrier, every other candidate the network's."""
+    from paper_2604_24091_amd import workloads as W
+    from oracle import akmc_oracle as O
+    rng = np.random.default_rng(12)
+    spec = W.random_lattice(rng, (6, 6, 6), 5, 6, solute_total=0.05)
+    o = O.Oracle(spec)
+    env_all = o.encode_env_sites(np.arange(spec.n_sites, dtype=np.int32)).reshape(-1, 27)
+    # Training rows: only all-Fe environments with Fe moving.
+    train = np.zeros((10, 27), dtype=np.uint8)
+    train[3, 0] = 4                                   # a vacancy row: not a training row
+    b = M.ood_bounds(train, 5)
+    assert list(b["seen"]) == [0] and b["max"].shape == (4, 5)
+    assert np.all(b["max"][:, 0] == [7, 6, 7, 6]) and np.all(b["max"][:, 1:] == 0)
+    ind = M.in_distribution(b, env_all, 5)
+    allfe = np.all(env_all == 0, axis=1)
+    assert np.array_equal(ind, allfe)
+    # One extra Cu in N2(j) takes a row out; a Cu mover too.
+    e = np.zeros((2, 27), dtype=np.uint8)
+    e[0, 22] = 1
+    e[1, 0] = 1
+    assert not M.in_distribution(b, e, 5).any()
+    p = M.init_params(5, rng, mu=0.6, sigma=0.05)
+    model = M.barrier_model(p, b, o, 5)
+    ea = model(o.occ, o.slots)
+    _, ea_pair = o.rates_sites(o.slots)
+    env = o.encode_env_sites(o.slots).reshape(-1, 27)
+    ind = M.in_distribution(b, env, 5) & np.isfinite(ea_pair.reshape(-1))
+    flat = ea.reshape(-1)
+    assert np.array_equal(np.isinf(flat), np.isinf(ea_pair.reshape(-1)))
+    assert np.array_equal(flat[~ind], ea_pair.reshape(-1)[~ind])
+    if ind.any():
+        np.testing.assert_array_equal(flat[ind], M.predict_ea(p, env[ind], 5, True))
+
+
+def test_follower_reproduces_the_plain_oracle_and_flags_a_wrong_log():
+    """The Python follow mode with pair barriers, on the C oracle's own log:
+    every choice inside its interval, and the final state, digest and time
+    equal to the oracle run bit for bit; a log with one wrong direction is a
+    structural mismatch, and a log whose uniforms belong to another stream
+    puts choices outside their intervals."""
+    from paper_2604_24091_amd import workloads as W
+    from oracle import akmc_oracle as O
+    from oracle.follow import Follower
+    spec = W.random_lattice(np.random.default_rng(13), (5, 5, 5), 5, 7, solute_total=0.3)
+    ref = O.Oracle(spec)
+    _, log = ref.run(500, log=True)
+    geo = O.Oracle(spec)
+    pair = lambda occ, slots: geo.rates_sites(slots, occ)[1]
+    f = Follower(spec, pair)
+    r = f.follow(log)
+    assert r["mismatches"] == 0 and r["n_differ"] == 0 and r["events"] == 500
+    assert r["max_select_violation"] == 0.0 and r["max_gamma_rel"] < 1e-15 and r["max_dt_rel"] < 1e-15
+    assert np.array_equal(f.occ, ref.occ) and f.digest == ref.state.digest and f.t == ref.state.t
+    bad = log.copy()
+    bad["dir"][100] = (bad["dir"][100] + 1) % 8
+    r = Follower(spec, pair).follow(bad)
+    assert r["mismatches"] == 1 and r["events"] <= 100
+    other = W.LatticeSpec(**{**spec.__dict__, "stream_id": spec.stream_id + 1})
+    r = Follower(other, pair).follow(log)
+    assert r["n_differ"] > 100
