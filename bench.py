@@ -153,6 +153,53 @@ def cpu_baseline(spec, n_events, local=False):
                       "(%.1f s)" % (done, how, dt)}
 
 
+def cpu_baseline_replicas(n_events):
+    """The oracle (full rate recompute per event, binary64) on the 256-replica
+    ensemble, one replica per task over every host thread (the C oracle
+    releases the interpreter while it runs)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import akmc_oracle as O
+    from paper_2604_24091_amd import workloads as W
+    reps = W.rpv_replicas()
+    oracles = [O.Oracle(r) for r in reps]
+    # the box's CPU share: at most 16 threads per GPU, whatever the host shows
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        done = sum(ex.map(lambda o: o.run(n_events), oracles))
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "events/s", "cores": threads, "host_cpu": host_cpu(),
+            "kind": "oracle",
+            "sample": "first %d events of each of the 256 replicas (16^3..48^3 cells, 1-20 vacancies), "
+                      "binary64, full rate recompute per event, one replica per task on %d threads "
+                      "(%.1f s)" % (n_events, threads, dt)}
+
+
+def cpu_rate_baseline(spec, occ, sites, gpu_rates):
+    """The oracle's rate evaluation (binary64, one thread) on a sample of the
+    sweep's sites, timed; the same oracle rates are the reference of the
+    binary32 sweep's per-result error on those sites (state after the timed
+    steps)."""
+    from oracle import akmc_oracle as O
+    from paper_2604_24091_amd import workloads as W
+    o = O.Oracle(W.LatticeSpec(**{**spec.__dict__, "occ": occ}))
+    t0 = time.perf_counter()
+    ro, eo = o.rates_sites(sites)
+    dt = time.perf_counter() - t0
+    m = ro > 0
+    g = gpu_rates.astype(np.float64)
+    rel = np.abs(g[m] - ro[m]) / ro[m]
+    base = {"value": sites.size * 8 / dt, "unit": "rate evals/s", "cores": 1, "host_cpu": host_cpu(),
+            "kind": "oracle",
+            "sample": "8 jump rates of %d random sites of the 4.2M-site lattice, binary64, one thread "
+                      "(%.2f s)" % (sites.size, dt)}
+    err = {"reference": "binary64 oracle", "sites": int(sites.size), "candidates": int(m.sum()),
+           "mask_equal": bool(np.array_equal(g > 0, m)),
+           "max_rel_rate": float(rel.max()), "median_rel_rate": float(np.median(rel)),
+           "p999_rel_rate": float(np.quantile(rel, 0.999))}
+    return base, err
+
+
 def bench_forms(args, torch, akmc, W, stream):
     forms = {}
     # binary64 plain path on the same lattice.
@@ -182,6 +229,28 @@ def bench_forms(args, torch, akmc, W, stream):
     del out
     forms["fp32_vs_fp64"] = bench_fp32_error(torch, akmc, W, stream)
 
+    # The two smaller single-lattice workloads, in full.
+    for name, fn, prec, n_ev in (("fe_cu_2k_fp64", W.fe_cu_2k, akmc.FP64, 10_000),
+                                 ("rpv_524k_fp32", W.rpv_524k, akmc.FP32, 1_000_000)):
+        sp = fn()
+        lw = akmc.Lattice(sp, precision=prec, stream=stream)
+        with torch.cuda.stream(stream):
+            lw.step(min(n_ev, 10_000))           # warm-up launch
+            torch.cuda.synchronize()
+            a, b2 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            lw.step(n_ev)
+            b2.record(stream)
+            torch.cuda.synchronize()
+        dt = a.elapsed_time(b2) * 1e-3
+        _, _, sm = lw.read()
+        lw.close()
+        forms[name] = {"events": n_ev, "sites": sp.n_sites, "vacancies": len(sp.vacancy_sites()),
+                       "precision": "binary64" if prec == akmc.FP64 else
+                                    "binary32 energies/rates, binary64 sums and time",
+                       "events_per_s": n_ev / dt, "us_per_event": dt * 1e6 / n_ev,
+                       "frozen": int(sm.frozen)}
+
     # Batched voxel ensemble: 256 independent replicas, one persistent launch.
     reps = W.rpv_replicas()
     params = [akmc.make_params(r, precision=akmc.FP32) for r in reps]
@@ -192,20 +261,28 @@ def bench_forms(args, torch, akmc, W, stream):
     sched = akmc.Schedule(chosen.group_lanes, chosen.waves_per_block, chosen.blocks, 1,
                           args.batch_events)
     akmc.batch_set_schedule(b, sched)
-    akmc.batch_step(b, args.batch_events)           # capture + warm
+    akmc.batch_step(b, 2000)                        # warm
     torch.cuda.synchronize()
+    busy0 = np.array([akmc.batch_state_read(b, r).loop_seconds for r in range(len(reps))])
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     akmc.batch_step(b, args.batch_events)
     e1.record(stream)
     torch.cuda.synchronize()
     dt = e0.elapsed_time(e1) * 1e-3
+    busy = np.array([akmc.batch_state_read(b, r).loop_seconds for r in range(len(reps))]) - busy0
     forms["batched"] = {"events_per_s": len(reps) * args.batch_events / dt,
                         "replicas": len(reps), "events_per_replica": args.batch_events,
+                        "wall_s": dt,
+                        "replica_seconds": {"max": float(busy.max()), "mean": float(busy.mean()),
+                                            "min": float(busy.min()),
+                                            "p99": float(np.quantile(busy, 0.99))},
+                        "tail_max_over_mean": float(busy.max() / busy.mean()),
+                        "slowest_replica_events_per_s": args.batch_events / float(busy.max()),
                         "sites_total": int(sum(r.n_sites for r in reps)),
                         "schedule": {"group_lanes": chosen.group_lanes,
                                      "waves_per_block": chosen.waves_per_block,
-                                     "hipgraph": 1}}
+                                     "hipgraph": 1, "chunk_events": args.batch_events}}
     akmc.batch_destroy(b)
     del ws
     if args.surrogate_samples > 0:
@@ -333,7 +410,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--events", type=int, default=100_000, help="events per step")
-    ap.add_argument("--batch-events", type=int, default=2_000, help="events per replica (batched form)")
+    ap.add_argument("--batch-events", type=int, default=100_000, help="events per replica (batched form)")
+    ap.add_argument("--cpu-replica-events", type=int, default=3_000,
+                    help="oracle events per replica of the all-core ensemble baseline")
+    ap.add_argument("--cpu-rate-sites", type=int, default=100_000,
+                    help="sites of the oracle's rate-evaluation sample")
     ap.add_argument("--cpu-events", type=int, default=30_000, help="oracle sample size (about 15 s)")
     ap.add_argument("--cpu-local-events", type=int, default=800_000,
                     help="sample of the oracle's local-refresh mode (about 10 s)")
@@ -411,6 +492,31 @@ def main():
     loop_ms = float(np.mean([a.elapsed_time(b) for a, b in loops]))
     occ, slots, summ = lat.read()
     assert summ.n_events == args.events * (args.steps + args.warmup)
+    rng = np.random.default_rng(77)
+    sample_sites = np.sort(rng.choice(spec.n_sites, min(args.cpu_rate_sites, spec.n_sites),
+                                      replace=False)).astype(np.int32)
+    sample_rates = rates[torch.as_tensor(sample_sites.astype(np.int64), device="cuda")].double().cpu().numpy()
+    # Plain fill and copy of the sweep's output array: the HBM rate this GPU
+    # sustains for the same bytes, measured next to the vendor peak.
+    other = torch.empty_like(rates)
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            rates.fill_(1.0)
+            other.copy_(rates)
+        torch.cuda.synchronize()
+        f0, f1, c1 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        f0.record(stream)
+        for _ in range(10):
+            rates.fill_(1.0)
+        f1.record(stream)
+        for _ in range(10):
+            other.copy_(rates)
+        c1.record(stream)
+        torch.cuda.synchronize()
+    nbytes = rates.numel() * rates.element_size()
+    fill_gbs = nbytes * 10 / (f0.elapsed_time(f1) * 1e-3) / 1e9
+    copy_gbs = 2 * nbytes * 10 / (f1.elapsed_time(c1) * 1e-3) / 1e9
+    del other
     assert np.array_equal(np.bincount(occ, minlength=5), np.bincount(spec.occ, minlength=5))
     lat.close()
 
@@ -446,7 +552,9 @@ def main():
                      "traffic": traffic,
                      "alg_bytes_per_launch": alg_bytes,
                      "launch_ms": sweep_ms,
-                     "launch_ms_each": [round(float(x), 5) for x in sweep_each]},
+                     "launch_ms_each": [round(float(x), 5) for x in sweep_each],
+                     "measured_fill_gbs": fill_gbs, "measured_copy_gbs": copy_gbs,
+                     "frac_of_measured_fill": achieved / fill_gbs},
         "event_loop": {"kernel": "k_event_loop (one 64-lane group, persistent)",
                        "events_per_s": args.events / (loop_ms * 1e-3),
                        "us_per_event": loop_ms * 1e3 / args.events,
@@ -464,6 +572,10 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(spec, args.cpu_events)
         line["cpu_baseline_local"] = cpu_baseline(spec, args.cpu_local_events, local=True)
+        line["cpu_baseline_rates"], line["fp32_vs_oracle"] = cpu_rate_baseline(
+            spec, occ, sample_sites, sample_rates)
+        if args.cpu_replica_events > 0:
+            line["cpu_baseline_replicas"] = cpu_baseline_replicas(args.cpu_replica_events)
     print(json.dumps(line), flush=True)
 
 

@@ -123,10 +123,14 @@ typedef struct akmc_summary {
     double gamma_tot;          /* total rate of the current state, Hz */
     uint64_t digest;
     int64_t species_count[8];  /* sites per species code */
-    int64_t n_neg_barrier;     /* current candidates with Ea < 0 */
+    int64_t n_neg_barrier;     /* current candidates (pair model) with Ea < 0 */
+    int64_t n_neg_reverse;     /* current candidates (pair model) with Ea < dE: the reverse
+                                  jump's barrier Ea - dE is negative */
     int64_t n_ood;             /* surrogate evaluations that fell back to the pair model */
     int32_t n_vacancies;
     int32_t frozen;            /* 1 if the last kmc_step stopped on Gamma_tot = 0 */
+    double loop_seconds;       /* device wall time the event loop has spent on this lattice
+                                  since create, summed over launches */
 } akmc_summary;
 
 typedef struct akmc_lattice *akmc_handle;
@@ -180,6 +184,17 @@ akmc_status akmc_rates_timing(akmc_handle h, void *start_event, void *stop_event
  * where it is and state_read reports frozen = 1; further steps do nothing.
  * A lattice without vacancies returns AKMC_ERR_FROZEN.  Asynchronous. */
 akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log);
+
+/* Barriers of the current candidates as the event loop last evaluated them
+ * (the pair model of Eq. 8's barrier, or the learned barrier with its
+ * pair-model fallback for a lattice with an attached network; the
+ * candidates in slot order, c = 8*slot + k; +inf for an inadmissible jump):
+ * d_ea_out receives n_vac*8 elements, double for AKMC_FP64 and float for
+ * AKMC_FP32.  The loop refreshes a candidate whenever its bonds change, so
+ * after every kmc_step these are the barriers of the current state.
+ * Asynchronous (a device copy on the handle's stream).  Errors: INVALID
+ * (NULL argument, no kmc_step has run on the handle yet), HIP. */
+akmc_status akmc_loop_barriers(akmc_handle h, void *d_ea_out);
 
 /* Synchronises the handle's stream and copies the state out.  occ_host
  * (uint8[N]) and slot_sites_host (int32[n_vac]) may be NULL; out may be

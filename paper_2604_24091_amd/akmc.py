@@ -48,8 +48,8 @@ class Event(C.Structure):
 class Summary(C.Structure):
     _fields_ = [("t", C.c_double), ("n_events", C.c_int64), ("gamma_tot", C.c_double),
                 ("digest", C.c_uint64), ("species_count", C.c_int64 * 8),
-                ("n_neg_barrier", C.c_int64), ("n_ood", C.c_int64),
-                ("n_vacancies", C.c_int32), ("frozen", C.c_int32)]
+                ("n_neg_barrier", C.c_int64), ("n_neg_reverse", C.c_int64), ("n_ood", C.c_int64),
+                ("n_vacancies", C.c_int32), ("frozen", C.c_int32), ("loop_seconds", C.c_double)]
 
 
 class TrainCfg(C.Structure):
@@ -94,6 +94,7 @@ def lib():
         L.akmc_rates_timing.argtypes = [vp, vp, vp]
         L.akmc_kmc_step.argtypes = [vp, C.c_int64, vp]
         L.akmc_state_read.argtypes = [vp, vp, vp, C.POINTER(Summary)]
+        L.akmc_loop_barriers.argtypes = [vp, vp]
         L.akmc_lattice_destroy.argtypes = [vp]
         L.akmc_cluster_scratch_bytes.argtypes = [vp, C.POINTER(sz)]
         L.akmc_cluster_hist.argtypes = [vp, C.c_int32, C.c_int64, vp, vp, sz]
@@ -126,7 +127,8 @@ def lib():
         L.akmc_status_string.restype = C.c_char_p
         L.akmc_last_error.restype = C.c_char_p
         for name in ("akmc_workspace_bytes", "akmc_lattice_create", "akmc_rates_eval",
-                     "akmc_rates_timing", "akmc_kmc_step", "akmc_state_read", "akmc_lattice_destroy",
+                     "akmc_rates_timing", "akmc_kmc_step", "akmc_loop_barriers", "akmc_state_read",
+                     "akmc_lattice_destroy",
                      "akmc_batch_workspace_bytes", "akmc_batch_create", "akmc_batch_set_schedule",
                      "akmc_batch_step", "akmc_batch_autotune", "akmc_batch_state_read",
                      "akmc_batch_destroy"):
@@ -233,6 +235,12 @@ def rates_timing(h: int, start=None, stop=None):
 
 def kmc_step(h: int, n_events: int, log=None):
     _check(lib().akmc_kmc_step(h, int(n_events), _ptr(log)), "kmc_step")
+
+
+def loop_barriers(h: int, ea_out):
+    """Barriers [n_vac][8] the event loop last evaluated (device tensor of
+    the handle's rate precision)."""
+    _check(lib().akmc_loop_barriers(h, _ptr(ea_out)), "loop_barriers")
 
 
 def state_read(h: int, occ_host: Optional[np.ndarray] = None,
@@ -438,6 +446,13 @@ class Lattice:
         ea = torch.empty_like(out) if with_ea else None
         rates_eval(self.h, mode, sites, n, out, ea)
         return (out, ea) if with_ea else out
+
+    def barriers(self):
+        """Device [n_vac][8] barriers the event loop last evaluated."""
+        import torch
+        out = torch.empty((max(self.n_vac, 1), 8), dtype=self.rate_dtype(), device=self.ws.device)
+        loop_barriers(self.h, out)
+        return out[:self.n_vac]
 
     def step(self, n_events: int, log: bool = False):
         import torch

@@ -156,7 +156,7 @@ LatDesc make_desc(const akmc_params *p, int nv) {
 }
 
 struct WsLayout {
-  size_t desc, state, order, queue, slots, scratch, occ, total;
+  size_t desc, state, order, queue, slots, scratch, trace, occ, total;
 };
 
 WsLayout ws_layout(int64_t nsites, int nv) {
@@ -167,7 +167,8 @@ WsLayout ws_layout(int64_t nsites, int nv) {
   w.order = o;   o += up(sizeof(int32_t));
   w.queue = o;   o += up(sizeof(int32_t));
   w.slots = o;   o += up(sizeof(int32_t) * (size_t)std::max(nv, 1));
-  w.scratch = o; o += up(sizeof(double) * 16 * (size_t)std::max(nv, 1));
+  w.scratch = o; o += up(sizeof(double) * 24 * (size_t)std::max(nv, 1));
+  w.trace = o;   o += up(sizeof(double) * 8 * (size_t)std::max(nv, 1));
   w.occ = o;     o += up((size_t)nsites);
   w.total = o;
   return w;
@@ -212,6 +213,8 @@ struct akmc_lattice {
   LatState *d_state;
   int32_t *d_order, *d_queue, *d_slots;
   double *d_scratch;
+  void *d_trace;        // barriers the event loop last evaluated, [nv][8]
+  bool stepped = false; // a kmc_step has filled d_trace
   uint8_t *d_occ;
   const unsigned char *mlp_blob = nullptr;
   LaunchTiming timing;  // events recorded by ALL_SITES launches (akmc_rates_timing)
@@ -261,6 +264,7 @@ akmc_status akmc_lattice_create(const akmc_params *p, const uint8_t *occ_host,
   h->d_queue = (int32_t *)(h->ws + lay.queue);
   h->d_slots = (int32_t *)(h->ws + lay.slots);
   h->d_scratch = (double *)(h->ws + lay.scratch);
+  h->d_trace = h->ws + lay.trace;
   h->d_occ = h->ws + lay.occ;
 
   LatState s0;
@@ -340,6 +344,7 @@ akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log) {
   const bool mlp = h->p.barrier_model == AKMC_BARRIER_MLP;
   if (mlp && !h->mlp_blob) return fail(AKMC_ERR_INVALID, "barrier_model MLP: attach weights with akmc_mlp_attach first");
   a.mlp_blob = h->mlp_blob;
+  a.ea_trace = h->d_trace;
   Schedule s{64, 1, 1};
   for (int64_t done = 0; done < n_events; done += kChunkEvents) {
     const int64_t n = std::min(kChunkEvents, n_events - done);
@@ -350,7 +355,18 @@ akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log) {
     hipError_t e = mlp ? launch_event_loop_mlp(a, full, h->p.n_species, h->stream)
                        : launch_event_loop(a, h->p.precision, full, s, h->stream);
     if (e != hipSuccess) return hip_fail(e, "kmc_step launch");
+    h->stepped = true;
   }
+  return AKMC_OK;
+}
+
+akmc_status akmc_loop_barriers(akmc_handle h, void *d_ea_out) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (!d_ea_out) return fail(AKMC_ERR_INVALID, "output is NULL");
+  if (!h->stepped) return fail(AKMC_ERR_INVALID, "no kmc_step has run on this lattice yet");
+  const size_t elem = h->p.precision == AKMC_FP32 ? sizeof(float) : sizeof(double);
+  HIP_TRY(hipMemcpyAsync(d_ea_out, h->d_trace, elem * 8 * (size_t)h->nv, hipMemcpyDeviceToDevice,
+                         h->stream));
   return AKMC_OK;
 }
 
@@ -379,23 +395,41 @@ static akmc_status read_state(hipStream_t stream, const LatDesc *d_desc, const L
   out->n_ood = s.n_ood;
   out->n_vacancies = nv;
   out->frozen = s.frozen;
+  {
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    out->loop_seconds = khz > 0 ? (double)s.busy_ticks / (1e3 * (double)khz) : 0.0;
+  }
   for (int64_t i = 0; i < nsites; ++i) out->species_count[occ[i] & 7] += 1;
   if (nv > 0) {
-    // Barriers of the current candidates, for the negative-barrier count.
+    // Pair-model barriers and energy changes of the current candidates, for
+    // the counts of negative forward and reverse barriers (compared in the
+    // precision the kernel computed them in; inadmissible jumps give
+    // Ea = +inf and dE = NaN and count in neither).
     hipError_t e = launch_rates_sites(d_desc, hd, d_occ, d_slots, nv, precision,
-                                      (void *)(d_scratch + 8 * nv), (void *)d_scratch, stream);
+                                      (void *)(d_scratch + 8 * nv), (void *)d_scratch, stream,
+                                      nullptr, (void *)(d_scratch + 16 * nv));
     if (e != hipSuccess) return hip_fail(e, "state_read barriers");
     HIP_TRY(hipStreamSynchronize(stream));
-    std::vector<double> ea64((size_t)nv * 8);
+    const size_t n = (size_t)nv * 8;
     if (precision == AKMC_FP32) {
-      std::vector<float> ea32((size_t)nv * 8);
-      HIP_TRY(hipMemcpy(ea32.data(), d_scratch, sizeof(float) * 8 * nv, hipMemcpyDeviceToHost));
-      for (size_t i = 0; i < ea32.size(); ++i) ea64[i] = ea32[i];
+      std::vector<float> ea(n), de(n);
+      HIP_TRY(hipMemcpy(ea.data(), d_scratch, sizeof(float) * n, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(de.data(), d_scratch + 16 * nv, sizeof(float) * n, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < n; ++i) {
+        out->n_neg_barrier += ea[i] < 0.0f;
+        out->n_neg_reverse += ea[i] < de[i];
+      }
     } else {
-      HIP_TRY(hipMemcpy(ea64.data(), d_scratch, sizeof(double) * 8 * nv, hipMemcpyDeviceToHost));
+      std::vector<double> ea(n), de(n);
+      HIP_TRY(hipMemcpy(ea.data(), d_scratch, sizeof(double) * n, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(de.data(), d_scratch + 16 * nv, sizeof(double) * n, hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < n; ++i) {
+        out->n_neg_barrier += ea[i] < 0.0;
+        out->n_neg_reverse += ea[i] < de[i];
+      }
     }
-    for (double v : ea64)
-      if (v < 0.0) out->n_neg_barrier += 1;
   }
   return AKMC_OK;
 }
@@ -498,7 +532,7 @@ BatchLayout batch_layout(int n_rep, const akmc_params *p, const int32_t *n_vac) 
     nvmax = std::max<int64_t>(nvmax, n_vac[r]);
   }
   b.slots = o;   o += up(sizeof(int32_t) * (size_t)std::max<int64_t>(ns, 1));
-  b.scratch = o; o += up(sizeof(double) * 16 * (size_t)nvmax);
+  b.scratch = o; o += up(sizeof(double) * 24 * (size_t)nvmax);
   b.occ = o;
   int64_t oo = 0;
   for (int r = 0; r < n_rep; ++r) {

@@ -59,6 +59,7 @@ struct LatState {
   int64_t n_ood;
   int32_t frozen;
   int32_t pad_;
+  int64_t busy_ticks;         // device wall-clock ticks the event loop has spent on this lattice
 };
 
 // Event-loop launch description.
@@ -76,6 +77,11 @@ struct LoopArgs {
   int32_t refresh_full;       // 1: refresh every slot after every event
   int64_t n_events;           // per lattice
   const unsigned char *mlp_blob;  // surrogate weights (barrier model MLP) or NULL
+  // NULL, or the barrier of every candidate as the loop last evaluated it,
+  // [slot][8] at element offset 8*slot_off of each lattice, in the rate
+  // precision (double, or float for binary32): after every event it holds
+  // the barriers of the current state (+inf for an inadmissible jump).
+  void *ea_trace;
 };
 
 // LDS carve-up of one lattice group in the event loop.  Every array is
@@ -160,7 +166,7 @@ struct LaunchTiming {
 hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h_desc, const uint8_t *occ,
                               const int32_t *sites, int64_t n_sites, int precision,
                               void *rates, void *ea, hipStream_t stream,
-                              const LaunchTiming *tm = nullptr);
+                              const LaunchTiming *tm = nullptr, void *de = nullptr);
 hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h_desc, const uint8_t *occ,
                             int precision, void *rates, void *ea, hipStream_t stream,
                             const LaunchTiming *tm = nullptr);

@@ -137,11 +137,12 @@ __device__ __forceinline__ Lds<Real> carve(unsigned char *base, const GroupLayou
 template <class Real>
 __device__ __forceinline__ double eval_box(const uint8_t *box, int k, int V, const Real *D1,
                                            const Real *D2, const Real *e0, Real nu, Real kT,
-                                           int &A_out) {
+                                           int &A_out, Real &ea_out) {
   const int jb = kBoxC + dir_sx(k) + 7 * dir_sy(k) + 49 * dir_sz(k);
   const int a4 = box[jb];
   const int A = a4 >> 2;
   A_out = A;
+  ea_out = Real(__builtin_huge_valf());
   if (A == V) return 0.0;
   uint32_t c1i = 0, c1j = 0;
 #pragma unroll
@@ -158,6 +159,7 @@ __device__ __forceinline__ double eval_box(const uint8_t *box, int k, int V, con
   c1j -= 1u << box[kBoxC];
   const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, D1 + 8 * A, D2 + 8 * A);
   const Real ea = e0[A] + Real(0.5) * de;
+  ea_out = ea;
   return (double)rate_from_barrier(ea, nu, kT);
 }
 
@@ -201,6 +203,7 @@ struct Runner {
   // moving species seen in training.
   uint32_t oodw[4], seen;
   double top_q;   // lane c < 8: partial c of the top tree level (cached between events)
+  Real *eat;      // barrier trace of this lattice (LoopArgs::ea_trace) or NULL
 
   __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
                     const int (&foot_)[8], unsigned char *lds)
@@ -360,12 +363,17 @@ struct Runner {
     int A = V;
     bool ood = false;
     float ea_pair = 0.f;
-    if (q < np) {
+    uint8_t *row = ml.senv + gp.gl * 32;
+    if (q >= np) {
+      // Rows of lanes without a candidate take part in the last tile: code S
+      // sets no input feature.
+#pragma unroll
+      for (int x = 0; x < kSlots; ++x) row[x] = (uint8_t)S;
+    } else {
       vv = s.aff[p0 + q];
       const int flip = (~k) & 7;
       const int jb = kBoxC + dir_sx(k) + 7 * dir_sy(k) + 49 * dir_sz(k);
       A = box[jb] >> 2;
-      uint8_t *row = ml.senv + gp.gl * 32;
       row[0] = (uint8_t)A;
       uint32_t c1i = 0, c1j = 0, c2i = 0, c2j = 0;
 #pragma unroll
@@ -415,10 +423,12 @@ struct Runner {
     double r = 0.0;
     const bool live = q < np && A != V;
     if (q < np) s.spec[vv * 8 + k] = (uint8_t)A;
+    float ea = __builtin_huge_valf();
     if (live) {
-      const float ea = ood ? ea_pair : mu + sigma * ml.yb[gp.gl];
+      ea = ood ? ea_pair : mu + sigma * ml.yb[gp.gl];
       r = (double)rate_from_barrier(ea, (float)nu, (float)kT);
     }
+    if (eat && q < np) eat[vv * 8 + k] = (Real)ea;
     n_ood += __popcll(gp.ballot(live && ood));
     return r;
   }
@@ -470,8 +480,10 @@ struct Runner {
         if (q < np) {
           vv = s.aff[p0 + q];
           int A;
-          r = eval_box<Real>(s.box + q * kBoxBytes, k, V, s.D1, s.D2, s.e0, nu, kT, A);
+          Real ea;
+          r = eval_box<Real>(s.box + q * kBoxBytes, k, V, s.D1, s.D2, s.e0, nu, kT, A, ea);
           s.spec[vv * 8 + k] = (uint8_t)A;
+          if (eat) eat[vv * 8 + k] = ea;
         }
       } else {
         r = eval_mlp_pass(np, q, k, p0, vv);
@@ -547,6 +559,7 @@ struct Runner {
     nv = d->nv;
     occ = a.occ + d->occ_off;
     int32_t *slots = a.slots + d->slot_off;
+    eat = a.ea_trace ? (Real *)a.ea_trace + d->slot_off * 8 : nullptr;
     akmc_event *evlog = a.log ? a.log + (int64_t)lat * a.log_stride : nullptr;
     const bool fp32 = sizeof(Real) == 4;
     for (int x = gl; x < 64; x += G) {
@@ -568,6 +581,7 @@ struct Runner {
     uint64_t dig = st->digest;
     int frozen = st->frozen;
     if (frozen) return;
+    const int64_t clk0 = wall_clock64();
 
     for (int v = gl; v < nv; v += G) {
       int X, Y, Z;
@@ -802,8 +816,10 @@ struct Runner {
         double r = 0.0;
         if (gl < 8) {
           int Ak;
-          r = eval_box<Real>(s.box, kk, V, s.D1, s.D2, s.e0, nu, kT, Ak);
+          Real ea;
+          r = eval_box<Real>(s.box, kk, V, s.D1, s.D2, s.e0, nu, kT, Ak, ea);
           s.spec[v * 8 + kk] = (uint8_t)Ak;
+          if (eat) eat[v * 8 + kk] = ea;
         }
         const double pfx = subgroup_prefix(r, kk);
         if (gl < 8) s.part[v * 8 + kk] = pfx;
@@ -827,6 +843,7 @@ struct Runner {
       st->gamma_tot = gtot;
       st->frozen = frozen;
       st->n_ood += n_ood;
+      st->busy_ticks += wall_clock64() - clk0;
     }
     gsync();
   }

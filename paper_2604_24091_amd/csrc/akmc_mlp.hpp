@@ -148,7 +148,8 @@ __device__ __forceinline__ void stage_rows8(unsigned short *dst, const unsigned 
 
 // One-hot input tile of 16 rows (bf16, pitch mlp_ld1(k1)) from 16 rows of
 // 32 species codes (the first kSlots used): the wavefront clears the tile,
-// then sets feature slot*S + code of every (row, slot).
+// then sets feature slot*S + code of every (row, slot); a code >= S sets
+// nothing (rows without a candidate).
 __device__ __forceinline__ void onehot_tile(const uint8_t *codes, unsigned short *atile, int S, int k1,
                                             int lane) {
   const int ld = mlp_ld1(k1);
@@ -158,7 +159,8 @@ __device__ __forceinline__ void onehot_tile(const uint8_t *codes, unsigned short
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   for (int u = lane; u < 16 * kSlots; u += 64) {
     const int row = u / kSlots, slot = u - row * kSlots;
-    atile[row * ld + slot * S + codes[row * 32 + slot]] = 0x3F80;  // bf16 1.0
+    const int code = codes[row * 32 + slot];
+    if (code < S) atile[row * ld + slot * S + code] = 0x3F80;  // bf16 1.0
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
                                                      const uint8_t *__restrict__ occ,
                                                      const int32_t *__restrict__ sites,
                                                      int64_t n_sites, Real *__restrict__ rates,
-                                                     Real *__restrict__ ea) {
+                                                     Real *__restrict__ ea, Real *__restrict__ de_out) {
   __shared__ Real sD1[64], sD2[64], se0[8];
   const int tid = threadIdx.x;
   if (tid < 64) { sD1[tid] = Tab<Real>::D1(d)[tid]; sD2[tid] = Tab<Real>::D2(d)[tid]; }
@@ -76,6 +76,7 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
   if (i < 0 || i >= 2 * g.ncell) {  // a listed site outside the lattice: no gather
     rates[c] = Real(__builtin_nan(""));
     if (ea) ea[c] = Real(__builtin_nan(""));
+    if (de_out) de_out[c] = Real(__builtin_nan(""));
     return;
   }
   int X, Y, Z;
@@ -83,7 +84,7 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
   const int JX = wrapc(X + dir_sx(k), g.X2), JY = wrapc(Y + dir_sy(k), g.Y2),
             JZ = wrapc(Z + dir_sz(k), g.Z2);
   const int A = occ[site_of(g, JX, JY, JZ)];
-  Real r, e;
+  Real r, e, de = Real(__builtin_nan(""));
   if (A == V) {
     r = Real(0);
     e = inf_of<Real>();
@@ -104,12 +105,13 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
     }
     c1i -= onehot(A);           // N1(i) without j
     c1j -= onehot(occ[i]);      // N1(j) without i
-    const Real de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, sD1 + 8 * A, sD2 + 8 * A);
+    de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, sD1 + 8 * A, sD2 + 8 * A);
     e = se0[A] + Real(0.5) * de;
     r = rate_from_barrier(e, Tab<Real>::nu(d), Tab<Real>::kT(d));
   }
   rates[c] = r;
   if (ea) ea[c] = e;
+  if (de_out) de_out[c] = de;
 }
 
 // ---------------------------------------------------------- bulk sweep
@@ -538,16 +540,16 @@ static void launch_timed(K k, dim3 grid, dim3 block, size_t lds, hipStream_t st,
 
 hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                               const int32_t *sites, int64_t n_sites, int precision, void *rates,
-                              void *ea, hipStream_t stream, const LaunchTiming *tm) {
+                              void *ea, hipStream_t stream, const LaunchTiming *tm, void *de) {
   if (n_sites <= 0) return hipSuccess;
   const int64_t nthreads = n_sites * 8;
   const unsigned blocks = (unsigned)((nthreads + 255) / 256);
   if (precision == AKMC_FP32)
     launch_timed(k_rates_sites<float>, dim3(blocks), dim3(256), 0, stream, tm, d_desc, occ, sites,
-                 n_sites, (float *)rates, (float *)ea);
+                 n_sites, (float *)rates, (float *)ea, (float *)de);
   else
     launch_timed(k_rates_sites<double>, dim3(blocks), dim3(256), 0, stream, tm, d_desc, occ, sites,
-                 n_sites, (double *)rates, (double *)ea);
+                 n_sites, (double *)rates, (double *)ea, (double *)de);
   return hipGetLastError();
 }
 

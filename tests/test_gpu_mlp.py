@@ -14,6 +14,8 @@ Tolerances:
   AdamW         one update from the GPU's own gradient: binary32 against the
                 binary64 formula, 1e-6 relative to the step size.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -302,6 +304,116 @@ def test_mlp_loop_trained_network_runs_physically(oracle_mod):
           "n_ood %d" % (ind.sum(), fin.sum(), rmse, s.n_ood), flush=True)
     assert ind.sum() >= fin.sum() // 2
     assert rmse < 40.0
+
+
+@pytest.fixture(scope="module")
+def trained_blob(oracle_mod):
+    """A network trained on the GPU for two epochs on every candidate of a
+    14^3-cell Fe-Cu-Ni-Mn lattice (3% solute, 25 vacancies), with its
+    out-of-distribution bounds fitted on the same rows.  Returns the blob,
+    the oracle's copy of its parameters and the oracle's bounds (computed
+    from the training rows in numpy, not read from the blob)."""
+    import torch
+    from oracle import mlp as M
+    spec = W.random_lattice(np.random.default_rng(101), (14, 14, 14), S, 25, solute_total=0.03)
+    o = oracle_mod.Oracle(spec)
+    sites = np.arange(spec.n_sites, dtype=np.int32)
+    env = o.encode_env_sites(sites).reshape(-1, 27)
+    _, ea = o.rates_sites(sites)
+    ea = ea.reshape(-1)
+    keep = np.isfinite(ea)
+    env, ea = np.ascontiguousarray(env[keep]), ea[keep].astype(np.float32)
+    mu, sigma = float(ea.mean()), float(ea.std())
+    blob = _blob(torch)
+    akmc.mlp_init(blob, S, 21, mu, sigma)
+    d_env = torch.as_tensor(env, device="cuda")
+    d_ea = torch.as_tensor(ea, device="cuda")
+    akmc.mlp_fit_ood(blob, S, d_env, len(env))
+    cfg = akmc.TrainCfg(batch=256, epochs=2, lr=2e-3, lr_final=1e-4, beta1=0.9, beta2=0.999, eps=1e-8,
+                        weight_decay=0.0, shuffle=1, seed=9)
+    work = torch.empty(akmc.mlp_train_workspace_bytes(S, 256), dtype=torch.uint8, device="cuda")
+    akmc.mlp_train(blob, S, d_env, d_ea, len(env), cfg, work)
+    torch.cuda.synchronize()
+    params, mu2, sg2 = akmc.mlp_get_params(blob, S)
+    p = akmc.unpack_params(params, S)
+    p["mu"], p["sigma"] = float(mu2), float(sg2)
+    return blob, p, M.ood_bounds(env, S)
+
+
+@pytest.mark.parametrize("nv,chunks", [(1, (1500, 2500)), (3, (1500, 2500)), (25, (2000, 4000)),
+                                       (akmc.MAX_VACANCIES, (150, 350))])
+def test_mlp_loop_trained_network_follows_oracle(oracle_mod, trained_blob, nv, chunks):
+    """A trained network drives the event loop.  After every chunk the
+    barriers the loop holds (akmc_loop_barriers: the in-loop forward of
+    every refreshed candidate, in one-slot passes, multi-slot passes and the
+    launch-start refresh) equal the oracle's learned barrier of the same
+    state (oracle/mlp.py with the same bfloat16 roundings; the pair barrier
+    for candidates out of distribution under the oracle's own bounds), and
+    the oracle follows the GPU's event log with those barriers: every choice
+    within its selection interval, Gamma_tot and dt of every event.
+
+    Tolerances.  Pair-model fallbacks: 1e-6 eV (binary32 of a binary64
+    value).  Network barriers: 2e-3 eV each, median 1e-5 eV, and at most 1%
+    of them beyond 1e-4 eV: the sides differ in binary32 against binary64
+    accumulation, which moves a hidden unit across a bfloat16 rounding
+    boundary only rarely.  Per event: the rates are exponentials of the
+    barriers, so Gamma_tot and the selection interval may differ by at most
+    the rate error exp(d/kT) - 1 of the largest barrier difference d seen,
+    and at most one choice in 1,000 may lie outside its exact interval."""
+    import torch
+    from oracle import mlp as M
+    from oracle.follow import Follower
+    banner("mlp loop trained vs oracle nv=%d" % nv)
+    blob, p, bounds = trained_blob
+    spec = W.random_lattice(np.random.default_rng(200 + nv), (14, 14, 14), S, nv, solute_total=0.03)
+    lat = akmc.Lattice(spec, precision=akmc.FP32, barrier_model=akmc.BARRIER_MLP)
+    akmc.mlp_attach(lat.h, blob)
+    o = oracle_mod.Oracle(spec)
+    model = M.barrier_model(p, bounds, o, S)
+    fol = Follower(spec, model)
+    kt = spec.kb * spec.temperature
+    n_done, worst, n_net, n_pair = 0, 0.0, 0, 0
+    for n in chunks:
+        buf = lat.step(n, log=True)
+        ea_g = lat.barriers().double().cpu().numpy()
+        torch.cuda.synchronize()
+        log = akmc.log_to_numpy(buf, n)
+        occ, slots, summ = lat.read()
+        n_done += n
+        assert summ.n_events == n_done and summ.frozen == 0
+        ea_o = model(occ, slots)
+        _, ea_pair = o.rates_sites(slots, occ)
+        fin = np.isfinite(ea_o)
+        assert np.array_equal(np.isfinite(ea_g), fin)
+        net = fin & (ea_o != ea_pair)          # the oracle evaluated the network
+        pair = fin & ~net
+        d_net = np.abs(ea_g[net] - ea_o[net])
+        d_pair = np.abs(ea_g[pair] - ea_o[pair])
+        n_net += int(net.sum())
+        n_pair += int(pair.sum())
+        if d_pair.size:
+            assert d_pair.max() <= 1e-6, d_pair.max()
+        if d_net.size:
+            assert d_net.max() <= 2e-3 and np.median(d_net) <= 1e-5, (d_net.max(), np.median(d_net))
+            assert np.mean(d_net > 1e-4) <= 0.01
+            worst = max(worst, float(d_net.max()))
+        f = fol.follow(log)
+        rate_bound = max(1e-5, math.expm1(worst / kt))
+        print("[gpu-case] nv=%d after %d events: %d network / %d pair barriers, network max diff "
+              "%.2e eV median %.2e; follow: violation %.2e, gamma %.2e, dt %.2e, %d outside" %
+              (nv, n_done, net.sum(), pair.sum(), d_net.max() if d_net.size else 0.0,
+               np.median(d_net) if d_net.size else 0.0, f["max_select_violation"], f["max_gamma_rel"],
+               f["max_dt_rel"], f["n_differ"]), flush=True)
+        assert f["mismatches"] == 0 and f["events"] == n
+        assert f["max_select_violation"] <= rate_bound
+        assert f["max_gamma_rel"] <= rate_bound and f["max_dt_rel"] <= rate_bound
+        assert f["n_differ"] <= 1 + n // 1000
+        assert np.array_equal(fol.occ, occ) and np.array_equal(fol.slots, slots)
+        assert fol.digest == summ.digest
+    lat.close()
+    assert n_net > 0
+    if nv == akmc.MAX_VACANCIES:
+        assert n_pair > 0                      # vacancy-rich environments fall back
 
 
 def test_mlp_attach_refuses_what_does_not_fit_lds():
