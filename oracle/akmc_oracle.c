@@ -379,12 +379,16 @@ static int half_dist(const orc_params *p, int32_t s, int32_t t) {
  * unchanged by the jump, so both modes give the same trajectory.  n_neg
  * counts the candidates each mode evaluates. */
 static int64_t run_events(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
-                          orc_state *st, int64_t n_events, orc_event *events, int local) {
+                          orc_state *st, int64_t n_events, orc_event *events, int local,
+                          double t_end) {
     int V = p->n_species - 1;
     double *rates = (double *)malloc(sizeof(double) * 8 * (size_t)(nv > 0 ? nv : 1));
     int64_t done = 0;
     if (local) all_rates(p, occ, slots, nv, rates, &st->n_neg_evaluated);
     for (int64_t e = 0; e < n_events; e++) {
+        /* Time horizon: an event starts only while t < t_end, so the event
+         * that reaches or crosses t_end is the last one. */
+        if (!(st->t < t_end)) break;
         if (!local) all_rates(p, occ, slots, nv, rates, &st->n_neg_evaluated);
         double u1, u2, g;
         orc_uniforms(p->seed, p->stream_id, st->n, &u1, &u2);
@@ -438,13 +442,22 @@ static int64_t run_events(const orc_params *p, uint8_t *occ, int32_t *slots, int
  * nothing changes).  log may be NULL. */
 int64_t orc_run(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
                 orc_state *st, int64_t n_events, orc_event *events) {
-    return run_events(p, occ, slots, nv, st, n_events, events, 0);
+    return run_events(p, occ, slots, nv, st, n_events, events, 0, INFINITY);
 }
 
 /* orc_run with the local refresh described at run_events. */
 int64_t orc_run_local(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
                       orc_state *st, int64_t n_events, orc_event *events) {
-    return run_events(p, occ, slots, nv, st, n_events, events, 1);
+    return run_events(p, occ, slots, nv, st, n_events, events, 1, INFINITY);
+}
+
+/* Advances the lattice to the physical time t_end: events run while
+ * t < t_end, at most max_events of them (a voxel evolved over a stretch of
+ * service time, Sec. III-C1).  Returns the number done (0 if t >= t_end
+ * already), or -4 if the state is frozen before the first event. */
+int64_t orc_run_until(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
+                      orc_state *st, double t_end, int64_t max_events, orc_event *events) {
+    return run_events(p, occ, slots, nv, st, max_events, events, 0, t_end);
 }
 
 /* Replays a given event log on (occ, slots, st) in binary64 and reports how

@@ -86,6 +86,9 @@ def lib():
         L.orc_run.restype = C.c_int64
         L.orc_run_local.argtypes = L.orc_run.argtypes
         L.orc_run_local.restype = C.c_int64
+        L.orc_run_until.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState),
+                                    C.c_double, C.c_int64, C.c_void_p]
+        L.orc_run_until.restype = C.c_int64
         L.orc_follow.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState),
                                  C.c_int64, C.c_void_p, _f64p]
         L.orc_follow.restype = None
@@ -172,6 +175,17 @@ class Oracle:
         done = fn(C.byref(self.p), self.occ, self.slots, self.slots.size,
                   C.byref(self.state), int(n_events),
                   buf.ctypes.data_as(C.c_void_p) if log else None)
+        if log:
+            return done, buf[:max(done, 0)]
+        return done
+
+    def run_until(self, t_end: float, max_events: int, log: bool = False):
+        """Events while t < t_end, at most max_events (the last event is the
+        one that reaches t_end)."""
+        buf = np.zeros(max(max_events, 1), dtype=EVENT_DTYPE) if log else None
+        done = lib().orc_run_until(C.byref(self.p), self.occ, self.slots, self.slots.size,
+                                   C.byref(self.state), C.c_double(t_end), int(max_events),
+                                   buf.ctypes.data_as(C.c_void_p) if log else None)
         if log:
             return done, buf[:max(done, 0)]
         return done
