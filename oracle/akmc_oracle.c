@@ -593,3 +593,233 @@ void orc_encode_env_sites(const orc_params *p, const uint8_t *occ, const int32_t
     for (int64_t a = 0; a < n; a++)
         for (int k = 0; k < 8; k++) orc_encode_env(p, occ, sites[a], k, out + (a * 8 + k) * 27);
 }
+
+/* ------------------------------------------- learned selection and time */
+
+/* AtomWorld's runtime forms (Sec. III-A1, III-A3), written out plainly:
+ *   - observation of a vacancy: the species of its 64 neighbours within
+ *     6.0 A (the cutoff and neighbour cap of Sec. IV-C; on the BCC lattice
+ *     these are shells 1-6 with 8, 6, 12, 24, 8, 6 sites);
+ *   - local policy (Eq. 1-2): a network maps the observation to 8 logits,
+ *     one per jump direction; an inadmissible jump's logit is -inf, the
+ *     others are scaled by 1/tau; the event is drawn from the softmax over
+ *     all candidates of the system, i.e. with weight exp(z_hat);
+ *   - Poisson time (Eq. 5-7): u(s) is a sum of per-vacancy network values
+ *     (the patch approximation of the dimensionless potential
+ *     u = Gamma_tot tau), and an event advances time by
+ *     dtau = (u(s) - Gamma_tot(s)/Gamma_tot(s') u(s')) / Gamma_tot(s),
+ *     with Gamma_tot the physical total rate of the pair model.
+ * Readings (the paper gives no sizes, order or activation):
+ *   - neighbour m of the observation is the m-th offset (dx, dy, dz), in
+ *     half-cell units, ordered by squared length, then dx, dy, dz
+ *     ascending;
+ *   - network: h1 = relu(b1 + sum_m W1[m][code_m]) (the one-hot first layer
+ *     as a sum of the rows the codes select, m = 0..63 in order),
+ *     h2 = relu(b2 + sum_i h1[i] W2[i][:]), out = b3 + sum_i h2[i] W3[i][:]
+ *     (i ascending), every operation a separately rounded binary32 add or
+ *     multiply; weights are bfloat16 values;
+ *   - logits scaled by inv_tau = 1/tau rounded to binary32 once; weights
+ *     exp(z_hat) in binary64;
+ *   - u(s) = sum of the per-vacancy values in slot order in binary64;
+ *   - a state s' with Gamma_tot(s') = 0 is frozen: its term is dropped
+ *     (dtau = u(s)/Gamma_tot(s)). */
+
+typedef struct {
+    int32_t n_species;   /* S */
+    int32_t hidden;      /* H <= 64 */
+    int32_t n_out;       /* 8 (policy) or 1 (Poisson network) */
+    int32_t pad_;
+    const float *w1;     /* [64][S][H] */
+    const float *b1;     /* [H] */
+    const float *w2;     /* [H][H], input-major */
+    const float *b2;     /* [H] */
+    const float *w3;     /* [H][n_out], input-major */
+    const float *b3;     /* [n_out] */
+} orc_patchnet;
+
+static int obs_off[64][3];
+static int obs_ready = 0;
+
+static void obs_build(void) {
+    if (obs_ready) return;
+    int n = 0;
+    const int shells[6] = {3, 4, 8, 11, 12, 16};
+    for (int sh = 0; sh < 6; sh++)
+        for (int dx = -4; dx <= 4; dx++)
+            for (int dy = -4; dy <= 4; dy++)
+                for (int dz = -4; dz <= 4; dz++) {
+                    int par = abs(dx) & 1;
+                    if ((abs(dy) & 1) != par || (abs(dz) & 1) != par) continue;
+                    if (dx * dx + dy * dy + dz * dz != shells[sh]) continue;
+                    obs_off[n][0] = dx;
+                    obs_off[n][1] = dy;
+                    obs_off[n][2] = dz;
+                    n++;
+                }
+    obs_ready = (n == 64);
+}
+
+/* Offset m of the observation, in half-cell units. */
+void orc_obs_offset(int m, int out[3]) {
+    obs_build();
+    out[0] = obs_off[m][0];
+    out[1] = obs_off[m][1];
+    out[2] = obs_off[m][2];
+}
+
+/* Site at half-cell offset (dx, dy, dz) from site s (all three of the same
+ * parity). */
+static int32_t offset_site(const orc_params *p, int32_t s, int dx, int dy, int dz) {
+    int b, x, y, z;
+    orc_decode(p, s, &b, &x, &y, &z);
+    int hx = wrap(2 * x + b + dx, 2 * p->lx);
+    int hy = wrap(2 * y + b + dy, 2 * p->ly);
+    int hz = wrap(2 * z + b + dz, 2 * p->lz);
+    int bb = hx & 1;
+    return orc_site(p, bb, (hx - bb) / 2, (hy - bb) / 2, (hz - bb) / 2);
+}
+
+/* Species codes of the 64-neighbour observation of a vacancy at site i. */
+void orc_observation(const orc_params *p, const uint8_t *occ, int32_t i, uint8_t out[64]) {
+    obs_build();
+    for (int m = 0; m < 64; m++)
+        out[m] = occ[offset_site(p, i, obs_off[m][0], obs_off[m][1], obs_off[m][2])];
+}
+
+/* Network outputs (n_out of them) for one observation. */
+void orc_patchnet_forward(const orc_patchnet *net, const uint8_t codes[64], float *out) {
+    int S = net->n_species, H = net->hidden;
+    float h1[64], h2[64];
+    for (int j = 0; j < H; j++) {
+        float acc = net->b1[j];
+        for (int m = 0; m < 64; m++) acc = acc + net->w1[((size_t)m * S + codes[m]) * H + j];
+        h1[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    for (int j = 0; j < H; j++) {
+        float acc = net->b2[j];
+        for (int i = 0; i < H; i++) {
+            float prod = h1[i] * net->w2[i * H + j];
+            acc = acc + prod;
+        }
+        h2[j] = acc > 0.0f ? acc : 0.0f;
+    }
+    for (int k = 0; k < net->n_out; k++) {
+        float acc = net->b3[k];
+        for (int i = 0; i < H; i++) {
+            float prod = h2[i] * net->w3[i * net->n_out + k];
+            acc = acc + prod;
+        }
+        out[k] = acc;
+    }
+}
+
+/* Selection weights exp(z_hat) of the 8 candidates of a vacancy at site i
+ * (0 for an inadmissible jump), and the logits themselves. */
+void orc_policy_weights(const orc_params *p, const uint8_t *occ, int32_t i,
+                        const orc_patchnet *pol, float inv_tau, double w[8], float z[8]) {
+    uint8_t codes[64];
+    orc_observation(p, occ, i, codes);
+    orc_patchnet_forward(pol, codes, z);
+    for (int k = 0; k < 8; k++) {
+        int32_t j = orc_nbr1(p, i, k);
+        w[k] = occ[j] == (uint8_t)(p->n_species - 1) ? 0.0 : exp((double)(z[k] * inv_tau));
+    }
+}
+
+/* u(s): the Poisson network's values of every vacancy, summed in slot
+ * order. */
+double orc_poisson_u(const orc_params *p, const uint8_t *occ, const int32_t *slots, int32_t nv,
+                     const orc_patchnet *pn) {
+    double u = 0.0;
+    for (int32_t v = 0; v < nv; v++) {
+        uint8_t codes[64];
+        float g;
+        orc_observation(p, occ, slots[v], codes);
+        orc_patchnet_forward(pn, codes, &g);
+        u += (double)g;
+    }
+    return u;
+}
+
+/* Eq. 7: the time increment of an event from s to s'. */
+double orc_poisson_dt(double u_s, double g_s, double u_s1, double g_s1) {
+    if (!(g_s1 > 0.0)) return u_s / g_s;
+    return (u_s - (g_s / g_s1) * u_s1) / g_s;
+}
+
+/* The event loop with a learned policy choosing the events (pol != NULL;
+ * else the rates do) and, with pn != NULL, Poisson time (Eq. 7); without
+ * pn, time follows p->time_mode with the physical total rate.  Every rate,
+ * weight and network value is recomputed before every event.  Returns the
+ * number of events done, or -4 if nothing can be chosen before the first. */
+int64_t orc_run_learned(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
+                        orc_state *st, int64_t n_events, orc_event *events,
+                        const orc_patchnet *pol, float inv_tau, const orc_patchnet *pn) {
+    int V = p->n_species - 1;
+    size_t nc = 8 * (size_t)(nv > 0 ? nv : 1);
+    double *rates = (double *)malloc(sizeof(double) * nc);
+    double *w = (double *)malloc(sizeof(double) * nc);
+    int64_t done = 0;
+    double g = 0.0;
+    all_rates(p, occ, slots, nv, rates, NULL);
+    for (int64_t c = 0; c < 8 * (int64_t)nv; c++) g += rates[c];
+    double u = pn ? orc_poisson_u(p, occ, slots, nv, pn) : 0.0;
+    for (int64_t e = 0; e < n_events; e++) {
+        const double *sel = rates;
+        if (pol) {
+            for (int32_t v = 0; v < nv; v++) {
+                float z[8];
+                orc_policy_weights(p, occ, slots[v], pol, inv_tau, w + 8 * v, z);
+            }
+            sel = w;
+        }
+        double u1, u2, wsum;
+        orc_uniforms(p->seed, p->stream_id, st->n, &u1, &u2);
+        int64_t c = orc_select(sel, 8 * (int64_t)nv, u1, &wsum);
+        if (c < 0 || !(g > 0.0)) {
+            st->gamma_tot = g;
+            free(rates);
+            free(w);
+            return done > 0 ? done : -4;
+        }
+        int32_t v = (int32_t)(c / 8);
+        int k = (int)(c % 8);
+        int32_t i = slots[v], j = orc_nbr1(p, i, k);
+        uint8_t a = occ[j];
+        occ[i] = a;
+        occ[j] = (uint8_t)V;
+        slots[v] = j;
+        double g1 = 0.0;
+        all_rates(p, occ, slots, nv, rates, NULL);
+        for (int64_t q = 0; q < 8 * (int64_t)nv; q++) g1 += rates[q];
+        double dt, u1s = 0.0;
+        if (pn) {
+            u1s = orc_poisson_u(p, occ, slots, nv, pn);
+            dt = orc_poisson_dt(u, g, u1s, g1);
+        } else {
+            dt = (p->time_mode == 1) ? 1.0 / g : -log(u2) / g;
+        }
+        if (events) {
+            orc_event *ev = &events[e];
+            memset(ev, 0, sizeof(*ev));
+            ev->n = st->n;
+            ev->slot = v;
+            ev->from_site = i;
+            ev->to_site = j;
+            ev->dir = (uint8_t)k;
+            ev->species = a;
+            ev->gamma_tot = g;
+            ev->dt = dt;
+        }
+        st->digest = digest_event(st->digest, st->n, i, j);
+        st->t += dt;
+        st->n += 1;
+        done += 1;
+        g = g1;
+        u = u1s;
+    }
+    st->gamma_tot = g;
+    free(rates);
+    free(w);
+    return done;
+}

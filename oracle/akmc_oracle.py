@@ -37,6 +37,36 @@ class OrcState(C.Structure):
                 ("gamma_tot", C.c_double), ("n_neg_evaluated", C.c_int64)]
 
 
+class OrcPatchNet(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("hidden", C.c_int32), ("n_out", C.c_int32),
+                ("pad_", C.c_int32),
+                ("w1", C.c_void_p), ("b1", C.c_void_p), ("w2", C.c_void_p),
+                ("b2", C.c_void_p), ("w3", C.c_void_p), ("b3", C.c_void_p)]
+
+
+class PatchNet:
+    """Weights of a local patch network (policy: n_out = 8; Poisson
+    network: n_out = 1) as binary32 arrays: w1 [64][S][H], b1 [H],
+    w2 [H][H], b2 [H], w3 [H][n_out], b3 [n_out]."""
+
+    def __init__(self, w1, b1, w2, b2, w3, b3):
+        self.w1 = np.ascontiguousarray(w1, dtype=np.float32)
+        self.b1 = np.ascontiguousarray(b1, dtype=np.float32)
+        self.w2 = np.ascontiguousarray(w2, dtype=np.float32)
+        self.b2 = np.ascontiguousarray(b2, dtype=np.float32)
+        self.w3 = np.ascontiguousarray(w3, dtype=np.float32)
+        self.b3 = np.ascontiguousarray(b3, dtype=np.float32)
+        self.S = self.w1.shape[1]
+        self.H = self.w1.shape[2]
+        self.n_out = self.w3.shape[1]
+        assert self.w1.shape[0] == 64 and self.w2.shape == (self.H, self.H)
+        assert self.b1.shape == (self.H,) and self.b2.shape == (self.H,)
+        assert self.w3.shape[0] == self.H and self.b3.shape == (self.n_out,)
+        self.c = OrcPatchNet(self.S, self.H, self.n_out, 0,
+                             *(a.ctypes.data for a in (self.w1, self.b1, self.w2, self.b2,
+                                                       self.w3, self.b3)))
+
+
 EVENT_DTYPE = np.dtype([("n", "<i8"), ("slot", "<i4"), ("from_site", "<i4"),
                         ("to_site", "<i4"), ("dir", "u1"), ("species", "u1"),
                         ("pad", "u1", (2,)), ("gamma_tot", "<f8"), ("dt", "<f8")])
@@ -100,6 +130,23 @@ def lib():
         L.orc_encode_env_sites.restype = None
         L.orc_barrier_counts.argtypes = [P, _u8p, _i32p, C.c_int32, _i64p]
         L.orc_barrier_counts.restype = None
+        NP = C.POINTER(OrcPatchNet)
+        L.orc_obs_offset.argtypes = [C.c_int, _i32p]
+        L.orc_obs_offset.restype = None
+        L.orc_observation.argtypes = [P, _u8p, C.c_int32, _u8p]
+        L.orc_observation.restype = None
+        L.orc_patchnet_forward.argtypes = [NP, _u8p, np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")]
+        L.orc_patchnet_forward.restype = None
+        L.orc_policy_weights.argtypes = [P, _u8p, C.c_int32, NP, C.c_float, _f64p,
+                                         np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")]
+        L.orc_policy_weights.restype = None
+        L.orc_poisson_u.argtypes = [P, _u8p, _i32p, C.c_int32, NP]
+        L.orc_poisson_u.restype = C.c_double
+        L.orc_poisson_dt.argtypes = [C.c_double] * 4
+        L.orc_poisson_dt.restype = C.c_double
+        L.orc_run_learned.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState), C.c_int64,
+                                      C.c_void_p, C.c_void_p, C.c_float, C.c_void_p]
+        L.orc_run_learned.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -190,6 +237,46 @@ class Oracle:
             return done, buf[:max(done, 0)]
         return done
 
+    def observation(self, i: int, occ=None):
+        occ = self.occ if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
+        out = np.zeros(64, dtype=np.uint8)
+        lib().orc_observation(C.byref(self.p), occ, int(i), out)
+        return out
+
+    def policy_weights(self, pol: "PatchNet", inv_tau: float, occ=None):
+        """[n_vac][8] selection weights exp(z_hat) and logits of the current
+        slots (weight 0 for an inadmissible jump)."""
+        occ = self.occ if occ is None else np.ascontiguousarray(occ, dtype=np.uint8)
+        nv = self.slots.size
+        w = np.zeros((nv, 8), dtype=np.float64)
+        z = np.zeros((nv, 8), dtype=np.float32)
+        for v in range(nv):
+            wv = np.zeros(8, dtype=np.float64)
+            zv = np.zeros(8, dtype=np.float32)
+            lib().orc_policy_weights(C.byref(self.p), occ, int(self.slots[v]), C.byref(pol.c),
+                                     C.c_float(inv_tau), wv, zv)
+            w[v], z[v] = wv, zv
+        return w, z
+
+    def poisson_u(self, pn: "PatchNet") -> float:
+        return lib().orc_poisson_u(C.byref(self.p), self.occ, self.slots, self.slots.size,
+                                   C.byref(pn.c))
+
+    def run_learned(self, n_events: int, pol: Optional["PatchNet"] = None, inv_tau: float = 1.0,
+                    pn: Optional["PatchNet"] = None, log: bool = False):
+        """Events chosen by the policy (or by the rates without one), time by
+        Eq. 7 with a Poisson network (or by time_mode without one)."""
+        buf = np.zeros(max(n_events, 1), dtype=EVENT_DTYPE) if log else None
+        done = lib().orc_run_learned(C.byref(self.p), self.occ, self.slots, self.slots.size,
+                                     C.byref(self.state), int(n_events),
+                                     buf.ctypes.data_as(C.c_void_p) if log else None,
+                                     C.cast(C.byref(pol.c), C.c_void_p) if pol else None,
+                                     C.c_float(inv_tau),
+                                     C.cast(C.byref(pn.c), C.c_void_p) if pn else None)
+        if log:
+            return done, buf[:max(done, 0)]
+        return done
+
     def follow(self, log_records):
         recs = np.ascontiguousarray(log_records, dtype=EVENT_DTYPE)
         out = np.zeros(5, dtype=np.float64)
@@ -225,6 +312,26 @@ class Oracle:
         out = np.zeros(2, dtype=np.int64)
         lib().orc_barrier_counts(C.byref(self.p), self.occ, self.slots, self.slots.size, out)
         return int(out[0]), int(out[1])
+
+
+def patchnet_forward(net: PatchNet, codes) -> np.ndarray:
+    c = np.ascontiguousarray(codes, dtype=np.uint8)
+    out = np.zeros(net.n_out, dtype=np.float32)
+    lib().orc_patchnet_forward(C.byref(net.c), c, out)
+    return out
+
+
+def obs_offsets() -> np.ndarray:
+    out = np.zeros((64, 3), dtype=np.int32)
+    for m in range(64):
+        o = np.zeros(3, dtype=np.int32)
+        lib().orc_obs_offset(m, o)
+        out[m] = o
+    return out
+
+
+def poisson_dt(u_s: float, g_s: float, u_s1: float, g_s1: float) -> float:
+    return lib().orc_poisson_dt(u_s, g_s, u_s1, g_s1)
 
 
 def philox(counter, key):
