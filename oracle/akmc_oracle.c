@@ -614,10 +614,10 @@ void orc_encode_env_sites(const orc_params *p, const uint8_t *occ, const int32_t
  *     half-cell units, ordered by squared length, then dx, dy, dz
  *     ascending;
  *   - network: h1 = relu(b1 + sum_m W1[m][code_m]) (the one-hot first layer
- *     as a sum of the rows the codes select, m = 0..63 in order),
- *     h2 = relu(b2 + sum_i h1[i] W2[i][:]), out = b3 + sum_i h2[i] W3[i][:]
- *     (i ascending), every operation a separately rounded binary32 add or
- *     multiply; weights are bfloat16 values;
+ *     as a sum of the rows the codes select, m = 0..63 in order, binary32
+ *     adds), h2 = relu(b2 + sum_i h1[i] W2[i][:]) and
+ *     out = b3 + sum_i h2[i] W3[i][:] (i ascending, each term one binary32
+ *     fused multiply-add); weights are bfloat16 values;
  *   - logits scaled by inv_tau = 1/tau rounded to binary32 once; weights
  *     exp(z_hat) in binary64;
  *   - u(s) = sum of the per-vacancy values in slot order in binary64;
@@ -697,18 +697,12 @@ void orc_patchnet_forward(const orc_patchnet *net, const uint8_t codes[64], floa
     }
     for (int j = 0; j < H; j++) {
         float acc = net->b2[j];
-        for (int i = 0; i < H; i++) {
-            float prod = h1[i] * net->w2[i * H + j];
-            acc = acc + prod;
-        }
+        for (int i = 0; i < H; i++) acc = fmaf(h1[i], net->w2[i * H + j], acc);
         h2[j] = acc > 0.0f ? acc : 0.0f;
     }
     for (int k = 0; k < net->n_out; k++) {
         float acc = net->b3[k];
-        for (int i = 0; i < H; i++) {
-            float prod = h2[i] * net->w3[i * net->n_out + k];
-            acc = acc + prod;
-        }
+        for (int i = 0; i < H; i++) acc = fmaf(h2[i], net->w3[i * net->n_out + k], acc);
         out[k] = acc;
     }
 }
