@@ -218,6 +218,24 @@ akmc_status akmc_cluster_scratch_bytes(akmc_handle h, size_t *bytes);
 akmc_status akmc_cluster_hist(akmc_handle h, int32_t species, int64_t max_size,
                               int64_t *d_hist, void *d_scratch, size_t scratch_bytes);
 
+/* Allocation-free variant of akmc_cluster_hist, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same histogram, with the
+ * parent and size arrays taken from a scratch array the library holds in
+ * its own device code object (32 MiB per device, kept until the process
+ * ends) instead of from a caller buffer.  The caller still passes d_hist
+ * (device int64[max_size + 1]).  The call allocates nothing and needs no
+ * clearing: the first kernel overwrites every scratch element it uses.
+ * All calls on one device share that one scratch array, so calls that
+ * overlap on one device (different streams, or several host threads) race
+ * and give wrong histograms; the caller serialises them.  Runs on the
+ * device the handle was created on and on the handle's stream.
+ * Errors: INVALID (as akmc_cluster_hist), UNSUPPORTED (more than
+ * AKMC_CLUSTER_STATIC_MAX_SITES sites), HIP. */
+#define AKMC_CLUSTER_STATIC_MAX_SITES 4194304
+akmc_status akmc_cluster_hist_noalloc(akmc_handle h, int32_t species, int64_t max_size,
+                                      int64_t *d_hist);
+
 /* Releases the host-side handle.  Does not free d_ws. */
 akmc_status akmc_lattice_destroy(akmc_handle h);
 

@@ -26,6 +26,7 @@ TIME_STOCHASTIC, TIME_MEAN = 0, 1
 BARRIER_PAIR, BARRIER_MLP = 0, 1
 RATES_VACANCIES, RATES_SITES, RATES_ALL_SITES = 0, 1, 2
 MAX_VACANCIES = 512
+CLUSTER_STATIC_MAX_SITES = 4194304
 
 
 class Params(C.Structure):
@@ -98,6 +99,7 @@ def lib():
         L.akmc_lattice_destroy.argtypes = [vp]
         L.akmc_cluster_scratch_bytes.argtypes = [vp, C.POINTER(sz)]
         L.akmc_cluster_hist.argtypes = [vp, C.c_int32, C.c_int64, vp, vp, sz]
+        L.akmc_cluster_hist_noalloc.argtypes = [vp, C.c_int32, C.c_int64, vp]
         L.akmc_batch_workspace_bytes.argtypes = [C.c_int32, P, vp, C.POINTER(sz)]
         L.akmc_batch_create.argtypes = [C.c_int32, P, vp, vp, vp, sz, vp, C.POINTER(vp)]
         L.akmc_batch_set_schedule.argtypes = [vp, C.POINTER(Schedule)]
@@ -128,7 +130,8 @@ def lib():
         L.akmc_last_error.restype = C.c_char_p
         for name in ("akmc_workspace_bytes", "akmc_lattice_create", "akmc_rates_eval",
                      "akmc_rates_timing", "akmc_kmc_step", "akmc_loop_barriers", "akmc_state_read",
-                     "akmc_lattice_destroy",
+                     "akmc_lattice_destroy", "akmc_cluster_scratch_bytes", "akmc_cluster_hist",
+                     "akmc_cluster_hist_noalloc",
                      "akmc_batch_workspace_bytes", "akmc_batch_create", "akmc_batch_set_schedule",
                      "akmc_batch_step", "akmc_batch_autotune", "akmc_batch_state_read",
                      "akmc_batch_destroy"):
@@ -265,6 +268,11 @@ def cluster_scratch_bytes(h: int) -> int:
 def cluster_hist(h: int, species: int, max_size: int, hist_out, scratch, scratch_bytes: int):
     _check(lib().akmc_cluster_hist(h, int(species), int(max_size), _ptr(hist_out), _ptr(scratch),
                                    int(scratch_bytes)), "cluster_hist")
+
+
+def cluster_hist_noalloc(h: int, species: int, max_size: int, hist_out):
+    _check(lib().akmc_cluster_hist_noalloc(h, int(species), int(max_size), _ptr(hist_out)),
+           "cluster_hist_noalloc")
 
 
 def batch_workspace_bytes(params: Sequence[Params], n_vac: Sequence[int]) -> int:

@@ -218,6 +218,7 @@ struct akmc_lattice {
   uint8_t *d_occ;
   const unsigned char *mlp_blob = nullptr;
   LaunchTiming timing;  // events recorded by ALL_SITES launches (akmc_rates_timing)
+  int device = 0;       // device current at create (where the workspace lives)
 };
 
 extern "C" {
@@ -254,6 +255,10 @@ akmc_status akmc_lattice_create(const akmc_params *p, const uint8_t *occ_host,
   h->p = *p;
   h->nv = nv;
   h->nsites = N;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return fail(AKMC_ERR_HIP, "hipGetDevice failed");
+  }
   h->stream = (hipStream_t)hip_stream;
   h->ws = (unsigned char *)d_ws;
   h->lay = lay;
@@ -464,6 +469,37 @@ akmc_status akmc_cluster_hist(akmc_handle h, int32_t species, int64_t max_size, 
   const hipError_t e = launch_cluster_hist(h->d_occ, h->p.lx, h->p.ly, h->p.lz, species, max_size,
                                            d_hist, parent, size, h->stream);
   if (e != hipSuccess) return hip_fail(e, "cluster_hist launch");
+  return AKMC_OK;
+}
+
+akmc_status akmc_cluster_hist_noalloc(akmc_handle h, int32_t species, int64_t max_size,
+                                      int64_t *d_hist) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (species < 0 || species >= h->p.n_species)
+    return fail(AKMC_ERR_INVALID, "species must lie in [0, n_species)");
+  if (max_size < 1 || max_size > h->nsites)
+    return fail(AKMC_ERR_INVALID, "max_size must lie in [1, number of sites]");
+  if (!d_hist) return fail(AKMC_ERR_INVALID, "histogram output is NULL");
+  if (h->nsites > AKMC_CLUSTER_STATIC_MAX_SITES)
+    return fail(AKMC_ERR_UNSUPPORTED,
+                "lattice has more sites than the library's cluster scratch holds "
+                "(AKMC_CLUSTER_STATIC_MAX_SITES = 4194304): use akmc_cluster_hist");
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != h->device) HIP_TRY(hipSetDevice(h->device));
+  int32_t *parent = nullptr, *size = nullptr;
+  hipError_t e = cluster_static_scratch(&parent, &size);
+  const char *what = "cluster scratch address (hipGetSymbolAddress)";
+  if (e == hipSuccess) {
+    e = launch_cluster_hist(h->d_occ, h->p.lx, h->p.ly, h->p.lz, species, max_size, d_hist,
+                            parent, size, h->stream);
+    what = "cluster_hist_noalloc launch";
+  }
+  if (cur != h->device) {
+    const hipError_t e2 = hipSetDevice(cur);
+    if (e == hipSuccess && e2 != hipSuccess) return hip_fail(e2, "hipSetDevice (restore)");
+  }
+  if (e != hipSuccess) return hip_fail(e, what);
   return AKMC_OK;
 }
 

@@ -13,7 +13,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
+#include "akmc.h"
 #include "akmc_device.hpp"
+
+// Scratch of the allocation-free histogram: parent and size arrays of up to
+// AKMC_CLUSTER_STATIC_MAX_SITES sites each (32 MiB per device).  Every
+// device holds its own copy; host code reaches it only through the address
+// that akmc::cluster_static_scratch resolves on that device (the name is a
+// host-side stand-in, not a device address).
+static __device__ __align__(256) int32_t scratch[2 * (size_t)AKMC_CLUSTER_STATIC_MAX_SITES];
 
 namespace akmc {
 
@@ -94,6 +105,25 @@ __global__ void k_cc_hist(int64_t n, const int *__restrict__ parent, const int *
 }
 
 }  // namespace
+
+hipError_t cluster_static_scratch(int32_t **parent, int32_t **size) {
+  static std::mutex mu;
+  static std::map<int, int32_t *> resolved;  // device -> device address of `scratch`
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = resolved.find(dev);
+  if (it == resolved.end()) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = resolved.emplace(dev, static_cast<int32_t *>(ptr)).first;
+  }
+  *parent = it->second;
+  *size = it->second + (size_t)AKMC_CLUSTER_STATIC_MAX_SITES;
+  return hipSuccess;
+}
 
 hipError_t launch_cluster_hist(const uint8_t *d_occ, int lx, int ly, int lz, int species,
                                int64_t max_size, int64_t *d_hist, int *d_parent, int *d_size,

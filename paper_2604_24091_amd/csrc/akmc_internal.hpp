@@ -155,6 +155,10 @@ hipError_t launch_queue_reset(int32_t *queue, hipStream_t stream);
 hipError_t launch_cluster_hist(const uint8_t *d_occ, int lx, int ly, int lz, int species,
                                int64_t max_size, int64_t *d_hist, int *d_parent, int *d_size,
                                hipStream_t st);
+// Device address, on the current device, of the library's own cluster
+// scratch (parent and size arrays of AKMC_CLUSTER_STATIC_MAX_SITES each),
+// resolved once per device.
+hipError_t cluster_static_scratch(int32_t **parent, int32_t **size);
 
 // Events that a launch records at the start and the end of its kernel's
 // execution (hipExtLaunchKernel), for callers that time kernels; either
