@@ -287,7 +287,95 @@ def bench_forms(args, torch, akmc, W, stream):
     del ws
     if args.surrogate_samples > 0:
         forms["surrogate"] = bench_surrogate(args, torch, akmc, W, stream)
+    if args.voxel_events > 0:
+        forms["voxel_ensemble"] = bench_voxels(args, torch, akmc, W, stream)
+    if args.learned_events > 0:
+        forms["learned_runtime"] = bench_learned(args, torch, akmc, W, stream)
     return forms
+
+
+def bench_voxels(args, torch, akmc, W, stream):
+    """Voxel ensemble of a wall thermal field (Sec. III-C): the Eq. 9 grid,
+    one 16^3-cell replica per voxel at the voxel's temperature, every
+    replica advanced to one physical-time horizon, with the persistent
+    groups pulling replicas heaviest first (Eq. 10 proxy computed on the
+    device) against the plain index order.  Fewer persistent groups than
+    replicas, so the order decides the tail."""
+    T = W.wall_thermal_field(32, 96)
+    gx, gz, tv, worst = akmc.voxel_grid(T, 0.6, W.KB_EV_PER_K, args.voxel_tol)
+    reps = W.voxel_replicas(tv, gx, gz, cells=16, max_vac=8)
+    params = [akmc.make_params(r, precision=akmc.FP32) for r in reps]
+    nv = [int(np.count_nonzero(r.occ == r.n_species - 1)) for r in reps]
+    res = {"field_samples": [32, 96], "grid": [gx, gz], "voxels": len(reps),
+           "eq9_tol": args.voxel_tol, "eq9_worst": worst,
+           "t_min_k": float(tv.min()), "t_max_k": float(tv.max()),
+           "vacancies": int(sum(nv))}
+    blocks = args.voxel_blocks
+    for name, order in (("priority", akmc.ORDER_PRIORITY), ("index", akmc.ORDER_INDEX)):
+        ws = torch.empty(akmc.batch_workspace_bytes(params, nv), dtype=torch.uint8, device="cuda")
+        b = akmc.batch_create(params, [r.occ for r in reps], ws, stream)
+        akmc.batch_set_schedule(b, akmc.Schedule(64, 1, blocks, 0, 1 << 30))
+        with torch.cuda.stream(stream):
+            akmc.batch_priority(b)     # evaluates every replica's candidates (no events)
+            torch.cuda.synchronize()
+            g = np.array([akmc.batch_state_read(b, r).gamma_tot for r in range(len(reps))])
+            t_end = args.voxel_events / float(np.median(g))
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            akmc.batch_run_until(b, t_end, 50 * args.voxel_events, order)
+            a1.record(stream)
+            torch.cuda.synchronize()
+        wall = a0.elapsed_time(a1) * 1e-3
+        ev = np.array([akmc.batch_state_read(b, r).n_events for r in range(len(reps))])
+        busy = np.array([akmc.batch_state_read(b, r).loop_seconds for r in range(len(reps))])
+        akmc.batch_destroy(b)
+        del ws
+        res[name] = {"wall_s": wall, "events": int(ev.sum()), "events_per_s": float(ev.sum()) / wall,
+                     "events_per_replica": {"min": int(ev.min()), "median": float(np.median(ev)),
+                                            "max": int(ev.max())},
+                     "replica_seconds_max": float(busy.max())}
+        res["t_end_s"] = t_end
+    res["persistent_groups"] = blocks
+    res["priority_speedup_vs_index"] = res["index"]["wall_s"] / res["priority"]["wall_s"]
+    return res
+
+
+def bench_learned(args, torch, akmc, W, stream):
+    """AtomWorld's runtime forms on the 4.2M-site lattice: events chosen by a
+    local policy network and time advanced by a Poisson network (both of
+    hidden width 64 on the 64-neighbour observation, seeded weights), against
+    the plain pair-rate loop on the same lattice."""
+    spec = W.rpv_4m()
+    rng = np.random.default_rng(2024)
+    S, H = spec.n_species, 64
+    nets = {}
+    for name, n_out, bias in (("policy", 8, 0.0), ("poisson", 1, 1.0)):
+        nb = akmc.PatchNetBlob(S, H, n_out)
+        nb.set(rng.normal(0, 0.5, (64, S, H)), rng.normal(0, 0.1, H), rng.normal(0, 0.12, (H, H)),
+               rng.normal(0, 0.1, H), rng.normal(0, 0.12, (H, n_out)), np.full(n_out, bias))
+        nets[name] = nb
+    res = {"hidden": H, "observation": "64 neighbours within 6.0 A (BCC shells 1-6)",
+           "events": args.learned_events}
+    for name, attach in (("pair", ()), ("policy", ("policy",)), ("poisson", ("poisson",)),
+                         ("policy_poisson", ("policy", "poisson"))):
+        lat = akmc.Lattice(spec, precision=akmc.FP32, stream=stream)
+        if "policy" in attach:
+            akmc.policy_attach(lat.h, nets["policy"].blob, 1.0)
+        if "poisson" in attach:
+            akmc.poisson_attach(lat.h, nets["poisson"].blob)
+        with torch.cuda.stream(stream):
+            lat.step(2000)
+            torch.cuda.synchronize()
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            lat.step(args.learned_events)
+            a1.record(stream)
+            torch.cuda.synchronize()
+        dt = a0.elapsed_time(a1) * 1e-3
+        lat.close()
+        res[name] = {"events_per_s": args.learned_events / dt, "us_per_event": dt * 1e6 / args.learned_events}
+    res["policy_poisson_vs_pair"] = res["policy_poisson"]["events_per_s"] / res["pair"]["events_per_s"]
+    return res
 
 
 def bench_fp32_error(torch, akmc, W, stream):
@@ -425,6 +513,12 @@ def main():
                     help="training+held-out candidates of the learned-barrier form (0 = skip it)")
     ap.add_argument("--surrogate-epochs", type=int, default=1)
     ap.add_argument("--surrogate-events", type=int, default=20_000)
+    ap.add_argument("--voxel-events", type=int, default=20_000,
+                    help="median events per voxel to the ensemble's time horizon (0 = skip)")
+    ap.add_argument("--voxel-tol", type=float, default=0.02, help="Eq. 9 tolerance of the voxel grid")
+    ap.add_argument("--voxel-blocks", type=int, default=128, help="persistent groups of the ensemble")
+    ap.add_argument("--learned-events", type=int, default=20_000,
+                    help="events per form of the learned runtime (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise pass over 256 MiB (reads 256 MiB, writes "
                          "256 MiB): the reference for the HBM byte counters")

@@ -185,6 +185,16 @@ akmc_status akmc_rates_timing(akmc_handle h, void *start_event, void *stop_event
  * A lattice without vacancies returns AKMC_ERR_FROZEN.  Asynchronous. */
 akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log);
 
+/* Advances the lattice toward the physical time t_end (a voxel evolved
+ * over a stretch of service time, Sec. III-C1): an event starts only while
+ * t < t_end, so the event that reaches or passes t_end is the last one; at
+ * most max_events events in this call.  d_log: device array of max_events
+ * records or NULL (only the first n_done are written; n_done is the change
+ * of summary.n_events).  Chunked calls continue exactly like one call.
+ * Asynchronous.  Errors: INVALID (NaN t_end, max_events < 0), FROZEN (no
+ * vacancies), UNSUPPORTED (as kmc_step). */
+akmc_status akmc_kmc_run_until(akmc_handle h, double t_end, int64_t max_events, akmc_event *d_log);
+
 /* Barriers of the current candidates as the event loop last evaluated them
  * (the pair model of Eq. 8's barrier, or the learned barrier with its
  * pair-model fallback for a lattice with an attached network; the
@@ -291,6 +301,117 @@ akmc_status akmc_batch_state_read(akmc_batch b, int32_t r, uint8_t *occ_host,
                                   int32_t *slot_sites_host, akmc_summary *out);
 
 akmc_status akmc_batch_destroy(akmc_batch b);
+
+/* ------------------------------------------------------ voxel ensemble */
+
+/* Temperature-guided discretisation (Sec. III-C1): a reactor-vessel wall
+ * section is split into a uniform n_x by n_z grid of voxels so that inside
+ * every voxel the relative rate variation of Eq. 9, E dT/(kB T^2), stays
+ * within tol, with dT the spread (max - min) of the field's samples in the
+ * voxel and T their mean.  The grid with the fewest voxels is chosen; among
+ * equal counts, the one with the fewest columns.
+ *   T        host double[nz][nx] samples, x (through the wall) fastest, K
+ *   e_eff    effective barrier E of Eq. 9, eV (> 0); kb eV/K; tol > 0
+ *   t_vox    host double[nx*nz] capacity; receives the n_z*n_x voxel
+ *            temperatures (means of their samples, summed row by row),
+ *            voxel (b, a) at b*n_x + a; voxel a spans the sample columns
+ *            floor(a*nx/n_x) .. floor((a+1)*nx/n_x) - 1, rows likewise
+ *   worst    largest Eq. 9 variation of the chosen voxels (may be NULL)
+ * Host only.  Errors: INVALID (NULL pointers, sizes < 1, non-finite or
+ * non-positive samples or parameters). */
+akmc_status akmc_voxel_grid(const double *T, int32_t nx, int32_t nz, double e_eff, double kb,
+                            double tol, int32_t *n_x, int32_t *n_z, double *t_vox, double *worst);
+
+/* Dispatch orders of akmc_batch_run_until. */
+#define AKMC_ORDER_PRIORITY 0  /* workload proxy of Eq. 10, heaviest first */
+#define AKMC_ORDER_INDEX    1  /* replica index */
+#define AKMC_ORDER_CREATE   2  /* the order fixed at create */
+
+/* Dynamic voxel scheduling (Sec. III-C2): the workload proxy of Eq. 10,
+ * W_r = M_r exp(-E_r / kB T_r), of every replica from its current state
+ * (M_r: admissible candidates; E_r: their mean barrier, summed in candidate
+ * order in binary64; T_r: the replica's temperature), computed on the
+ * device, and the queue order of the next launch set to decreasing W_r
+ * (equal weights by index).  d_w_out: device double[n_rep] or NULL;
+ * d_order_out: device int32[n_rep] receiving the order (replica indices,
+ * first dispatched first) or NULL.  Before the first launch on the batch a
+ * launch with no events evaluates the barriers.  Asynchronous.  Errors:
+ * INVALID, HIP. */
+akmc_status akmc_batch_priority(akmc_batch b, double *d_w_out, int32_t *d_order_out);
+
+/* Advances every replica toward t_end (as akmc_kmc_run_until, at most
+ * max_events_per_replica events each), the persistent groups pulling
+ * replicas in the given order (AKMC_ORDER_*); AKMC_ORDER_PRIORITY first
+ * recomputes the Eq. 10 order from the current states.  The order changes
+ * only which replica runs when, never a replica's events.  Asynchronous.
+ * Errors: INVALID (NaN t_end, negative count, unknown order), HIP. */
+akmc_status akmc_batch_run_until(akmc_batch b, double t_end, int64_t max_events_per_replica,
+                                 int32_t order);
+
+/* ------------------------------------------------ learned runtime forms */
+
+/* AtomWorld's runtime at simulation time (Sec. III-A): a local policy
+ * network chooses the events and a Poisson time network advances physical
+ * time, both on each vacancy's 64-neighbour observation (the species of the
+ * sites within 6.0 A, the neighbour cap of Sec. IV-C; BCC shells 1-6, the
+ * m-th neighbour being the m-th offset ordered by length, then x, y, z).
+ * Network (the paper gives no architecture; this is the library's): hidden
+ * width H <= 64, n_out outputs,
+ *   h1 = relu(b1 + sum_m W1[m][code_m])          (m = 0..63, binary32 adds)
+ *   h2 = relu(b2 + sum_i h1[i] W2[i][:])          (binary32 fma, i ascending)
+ *   out = b3 + sum_i h2[i] W3[i][:]                (binary32 fma, i ascending)
+ * with bfloat16 weights (W1, W2, W3) and binary32 biases.
+ *   Policy (n_out = 8, Eq. 1-2): logit z_k of jump direction k; an
+ *     inadmissible jump (onto a vacancy) is masked, the others scaled by
+ *     1/tau (rounded to binary32 once); the event is drawn from the softmax
+ *     over all candidates, i.e. with weight exp(z_k/tau) in binary64 in the
+ *     same tree and residence-time selection as the rates.
+ *   Poisson network (n_out = 1, Eq. 5-7): u(s) = sum over vacancies of the
+ *     network's value; an event s -> s' advances time by
+ *     (u(s) - Gamma(s)/Gamma(s') u(s'))/Gamma(s), Gamma the pair model's
+ *     total rate (a frozen s' drops its term).
+ * Without a policy the rates choose; without a Poisson network time
+ * follows time_mode with the pair model's total rate.
+ *
+ * Blob: device memory of akmc_patchnet_blob_bytes, 256-byte aligned, owned
+ * by the caller. */
+akmc_status akmc_patchnet_blob_bytes(int32_t n_species, int32_t hidden, int32_t n_out, size_t *bytes);
+
+/* Writes a network into the blob (synchronous copy on the default stream):
+ * host_params binary32 [W1 (64*S*H, [m][s][j]), b1 (H), W2 (H*H, [i][j]),
+ * b2 (H), W3 (H*n_out, [i][k]), b3 (n_out)]; the weights are rounded to
+ * bfloat16 (to nearest, ties to even), the biases kept.  Errors: INVALID
+ * (S not in [2, 8], H not in [1, 64], n_out not 1 or 8, NULL, non-finite
+ * values), HIP. */
+akmc_status akmc_patchnet_set(void *d_blob, int32_t n_species, int32_t hidden, int32_t n_out,
+                              const float *host_params);
+
+/* Reads the stored parameters back (the rounded weights), same layout;
+ * host_params may be NULL to read only the sizes.  Synchronous. */
+akmc_status akmc_patchnet_get(const void *d_blob, int32_t *n_species, int32_t *hidden, int32_t *n_out,
+                              float *host_params);
+
+/* The network's outputs for a vacancy placed at each listed site (its 64
+ * neighbours as the lattice holds them): d_out float[n_sites][n_out]
+ * (NaN for a site outside the lattice).  The same device forward the
+ * event loop runs.  Asynchronous.  Errors: INVALID (species count differs
+ * from the lattice's, NULL), HIP. */
+akmc_status akmc_patchnet_eval(akmc_handle h, const void *d_blob, const int32_t *d_sites,
+                               int64_t n_sites, float *d_out);
+
+/* Lets the policy in d_blob (n_out = 8) choose this lattice's events from
+ * the next kmc_step on, with temperature tau > 0; NULL restores selection
+ * by the rates.  The blob is borrowed until detached.  Errors: INVALID
+ * (not a policy blob, species count, tau, lattice edges below 5 cells: the
+ * observation must hold 64 distinct sites), UNSUPPORTED (learned barrier
+ * model lattice; the networks and the rate tree need more than 160 KiB of
+ * LDS), HIP. */
+akmc_status akmc_policy_attach(akmc_handle h, const void *d_blob, float tau);
+
+/* Lets the Poisson network in d_blob (n_out = 1) advance this lattice's
+ * time (Eq. 7) from the next kmc_step on; NULL restores time_mode.  Errors
+ * as akmc_policy_attach. */
+akmc_status akmc_poisson_attach(akmc_handle h, const void *d_blob);
 
 /* ----------------------------------------------------- learned barrier */
 

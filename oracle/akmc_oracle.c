@@ -817,3 +817,88 @@ int64_t orc_run_learned(const orc_params *p, uint8_t *occ, int32_t *slots, int32
     free(w);
     return done;
 }
+
+/* Replays a given event log under the learned forms (as orc_run_learned)
+ * and reports how every recorded event agrees with the oracle's weights,
+ * total rate and time increment of the state it was taken from:
+ *   out[0] = max selection-interval violation relative to the weight total
+ *   out[1] = max relative difference of the recorded (physical) Gamma_tot
+ *   out[2] = max difference of the recorded dt relative to
+ *            max(|dt|, u(s)/Gamma(s) + |u(s')|/Gamma(s')) (the scale of the
+ *            two terms of Eq. 7; plain |dt| without a Poisson network)
+ *   out[3] = structural mismatches (index, sites, species, a weight-0 pick)
+ *   out[4] = events whose choice lies outside its exact interval
+ * The logged swaps are applied. */
+void orc_follow_learned(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
+                        orc_state *st, int64_t n_events, const orc_event *events,
+                        const orc_patchnet *pol, float inv_tau, const orc_patchnet *pn,
+                        double out[5]) {
+    int V = p->n_species - 1;
+    size_t nc = 8 * (size_t)(nv > 0 ? nv : 1);
+    double *rates = (double *)malloc(sizeof(double) * nc);
+    double *w = (double *)malloc(sizeof(double) * nc);
+    for (int q = 0; q < 5; q++) out[q] = 0.0;
+    for (int64_t e = 0; e < n_events; e++) {
+        const orc_event *ev = &events[e];
+        all_rates(p, occ, slots, nv, rates, NULL);
+        double g = 0.0;
+        for (int64_t c = 0; c < 8 * (int64_t)nv; c++) g += rates[c];
+        const double *sel = rates;
+        if (pol) {
+            for (int32_t v = 0; v < nv; v++) {
+                float z[8];
+                orc_policy_weights(p, occ, slots[v], pol, inv_tau, w + 8 * v, z);
+            }
+            sel = w;
+        }
+        double wsum = 0.0;
+        for (int64_t c = 0; c < 8 * (int64_t)nv; c++) wsum += sel[c];
+        double u1, u2;
+        orc_uniforms(p->seed, p->stream_id, st->n, &u1, &u2);
+        int64_t c = (int64_t)ev->slot * 8 + ev->dir;
+        int bad = (ev->n != st->n || ev->slot < 0 || ev->slot >= nv || ev->dir > 7);
+        if (!bad) {
+            double before = 0.0;
+            for (int64_t q = 0; q < c; q++) before += sel[q];
+            double after = before + sel[c];
+            double target = u1 * wsum, viol = 0.0;
+            if (before - target > viol) viol = before - target;
+            if (target - after > viol) viol = target - after;
+            if (viol / wsum > out[0]) out[0] = viol / wsum;
+            if (viol > 0.0) out[4] += 1.0;
+            if (!(sel[c] > 0.0)) bad = 1;
+            double dg = fabs(ev->gamma_tot - g) / g;
+            if (dg > out[1]) out[1] = dg;
+            int32_t i = slots[ev->slot], j = orc_nbr1(p, i, ev->dir);
+            if (ev->from_site != i || ev->to_site != j || ev->species != occ[j]) bad = 1;
+            if (!bad) {
+                double u_s = pn ? orc_poisson_u(p, occ, slots, nv, pn) : 0.0;
+                occ[i] = occ[j];
+                occ[j] = (uint8_t)V;
+                slots[ev->slot] = j;
+                double dt, scale;
+                if (pn) {
+                    double g1 = orc_gamma_tot(p, occ, slots, nv);
+                    double u_s1 = orc_poisson_u(p, occ, slots, nv, pn);
+                    dt = orc_poisson_dt(u_s, g, u_s1, g1);
+                    scale = fabs(u_s) / g + (g1 > 0.0 ? fabs(u_s1) / g1 : 0.0);
+                } else {
+                    dt = (p->time_mode == 1) ? 1.0 / g : -log(u2) / g;
+                    scale = fabs(dt);
+                }
+                if (fabs(dt) > scale) scale = fabs(dt);
+                double ddt = fabs(ev->dt - dt) / scale;
+                if (ddt > out[2]) out[2] = ddt;
+                st->digest = digest_event(st->digest, st->n, i, j);
+                st->t += dt;
+            }
+        }
+        if (bad) {
+            out[3] += 1.0;
+            break;
+        }
+        st->n += 1;
+    }
+    free(rates);
+    free(w);
+}

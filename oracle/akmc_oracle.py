@@ -147,6 +147,9 @@ def lib():
         L.orc_run_learned.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState), C.c_int64,
                                       C.c_void_p, C.c_void_p, C.c_float, C.c_void_p]
         L.orc_run_learned.restype = C.c_int64
+        L.orc_follow_learned.argtypes = [P, _u8p, _i32p, C.c_int32, C.POINTER(OrcState), C.c_int64,
+                                         C.c_void_p, C.c_void_p, C.c_float, C.c_void_p, _f64p]
+        L.orc_follow_learned.restype = None
         _lib = L
     return _lib
 
@@ -276,6 +279,18 @@ class Oracle:
         if log:
             return done, buf[:max(done, 0)]
         return done
+
+    def follow_learned(self, log_records, pol: Optional["PatchNet"] = None, inv_tau: float = 1.0,
+                       pn: Optional["PatchNet"] = None):
+        recs = np.ascontiguousarray(log_records, dtype=EVENT_DTYPE)
+        out = np.zeros(5, dtype=np.float64)
+        lib().orc_follow_learned(C.byref(self.p), self.occ, self.slots, self.slots.size,
+                                 C.byref(self.state), recs.size, recs.ctypes.data_as(C.c_void_p),
+                                 C.cast(C.byref(pol.c), C.c_void_p) if pol else None,
+                                 C.c_float(inv_tau),
+                                 C.cast(C.byref(pn.c), C.c_void_p) if pn else None, out)
+        return {"max_select_violation": out[0], "max_gamma_rel": out[1],
+                "max_dt_rel": out[2], "mismatches": int(out[3]), "n_differ": int(out[4])}
 
     def follow(self, log_records):
         recs = np.ascontiguousarray(log_records, dtype=EVENT_DTYPE)

@@ -25,6 +25,7 @@ REFRESH_LOCAL, REFRESH_FULL = 0, 1
 TIME_STOCHASTIC, TIME_MEAN = 0, 1
 BARRIER_PAIR, BARRIER_MLP = 0, 1
 RATES_VACANCIES, RATES_SITES, RATES_ALL_SITES = 0, 1, 2
+ORDER_PRIORITY, ORDER_INDEX, ORDER_CREATE = 0, 1, 2
 MAX_VACANCIES = 512
 CLUSTER_STATIC_MAX_SITES = 4194304
 
@@ -94,6 +95,19 @@ def lib():
         L.akmc_rates_eval.argtypes = [vp, C.c_int32, vp, C.c_int64, vp, vp]
         L.akmc_rates_timing.argtypes = [vp, vp, vp]
         L.akmc_kmc_step.argtypes = [vp, C.c_int64, vp]
+        L.akmc_kmc_run_until.argtypes = [vp, C.c_double, C.c_int64, vp]
+        L.akmc_voxel_grid.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp,
+                                      C.POINTER(C.c_double)]
+        L.akmc_batch_priority.argtypes = [vp, vp, vp]
+        L.akmc_batch_run_until.argtypes = [vp, C.c_double, C.c_int64, C.c_int32]
+        L.akmc_patchnet_blob_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.POINTER(sz)]
+        L.akmc_patchnet_set.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, vp]
+        L.akmc_patchnet_get.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int32), vp]
+        L.akmc_patchnet_eval.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.akmc_policy_attach.argtypes = [vp, vp, C.c_float]
+        L.akmc_poisson_attach.argtypes = [vp, vp]
         L.akmc_state_read.argtypes = [vp, vp, vp, C.POINTER(Summary)]
         L.akmc_loop_barriers.argtypes = [vp, vp]
         L.akmc_lattice_destroy.argtypes = [vp]
@@ -131,7 +145,10 @@ def lib():
         for name in ("akmc_workspace_bytes", "akmc_lattice_create", "akmc_rates_eval",
                      "akmc_rates_timing", "akmc_kmc_step", "akmc_loop_barriers", "akmc_state_read",
                      "akmc_lattice_destroy", "akmc_cluster_scratch_bytes", "akmc_cluster_hist",
-                     "akmc_cluster_hist_noalloc",
+                     "akmc_cluster_hist_noalloc", "akmc_kmc_run_until", "akmc_voxel_grid",
+                     "akmc_batch_priority", "akmc_batch_run_until", "akmc_patchnet_blob_bytes",
+                     "akmc_patchnet_set", "akmc_patchnet_get", "akmc_patchnet_eval",
+                     "akmc_policy_attach", "akmc_poisson_attach",
                      "akmc_batch_workspace_bytes", "akmc_batch_create", "akmc_batch_set_schedule",
                      "akmc_batch_step", "akmc_batch_autotune", "akmc_batch_state_read",
                      "akmc_batch_destroy"):
@@ -238,6 +255,64 @@ def rates_timing(h: int, start=None, stop=None):
 
 def kmc_step(h: int, n_events: int, log=None):
     _check(lib().akmc_kmc_step(h, int(n_events), _ptr(log)), "kmc_step")
+
+
+def kmc_run_until(h: int, t_end: float, max_events: int, log=None):
+    _check(lib().akmc_kmc_run_until(h, float(t_end), int(max_events), _ptr(log)), "kmc_run_until")
+
+
+def voxel_grid(T: np.ndarray, e_eff: float, kb: float, tol: float):
+    """(n_x, n_z, voxel temperatures [n_z*n_x], worst Eq. 9 variation) of a
+    field T[nz][nx] (host call)."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    nz, nx = T.shape
+    out = np.zeros(nx * nz, dtype=np.float64)
+    gx, gz, worst = C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib().akmc_voxel_grid(T.ctypes.data, nx, nz, float(e_eff), float(kb), float(tol),
+                                 C.byref(gx), C.byref(gz), out.ctypes.data, C.byref(worst)),
+           "voxel_grid")
+    return gx.value, gz.value, out[:gx.value * gz.value].copy(), worst.value
+
+
+def patchnet_blob_bytes(S: int, H: int, n_out: int) -> int:
+    n = C.c_size_t()
+    _check(lib().akmc_patchnet_blob_bytes(int(S), int(H), int(n_out), C.byref(n)), "patchnet_blob_bytes")
+    return n.value
+
+
+def patchnet_set(blob, S: int, H: int, n_out: int, params: np.ndarray):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().akmc_patchnet_set(_ptr(blob), int(S), int(H), int(n_out), p.ctypes.data), "patchnet_set")
+
+
+def patchnet_get(blob):
+    S, H, no = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().akmc_patchnet_get(_ptr(blob), C.byref(S), C.byref(H), C.byref(no), None), "patchnet_get")
+    n = 64 * S.value * H.value + H.value + H.value * H.value + H.value + H.value * no.value + no.value
+    out = np.zeros(n, dtype=np.float32)
+    _check(lib().akmc_patchnet_get(_ptr(blob), None, None, None, out.ctypes.data), "patchnet_get")
+    return S.value, H.value, no.value, out
+
+
+def patchnet_eval(h: int, blob, sites, n_sites: int, out):
+    _check(lib().akmc_patchnet_eval(h, _ptr(blob), _ptr(sites), int(n_sites), _ptr(out)), "patchnet_eval")
+
+
+def policy_attach(h: int, blob, tau: float = 1.0):
+    _check(lib().akmc_policy_attach(h, _ptr(blob), C.c_float(tau)), "policy_attach")
+
+
+def poisson_attach(h: int, blob):
+    _check(lib().akmc_poisson_attach(h, _ptr(blob)), "poisson_attach")
+
+
+def batch_priority(b: int, w_out=None, order_out=None):
+    _check(lib().akmc_batch_priority(b, _ptr(w_out), _ptr(order_out)), "batch_priority")
+
+
+def batch_run_until(b: int, t_end: float, max_events_per_replica: int, order: int = ORDER_PRIORITY):
+    _check(lib().akmc_batch_run_until(b, float(t_end), int(max_events_per_replica), int(order)),
+           "batch_run_until")
 
 
 def loop_barriers(h: int, ea_out):
@@ -470,6 +545,14 @@ class Lattice:
         kmc_step(self.h, n_events, buf)
         return buf
 
+    def run_until(self, t_end: float, max_events: int, log: bool = False):
+        import torch
+        buf = None
+        if log:
+            buf = torch.empty((max(max_events, 1), 40), dtype=torch.uint8, device=self.ws.device)
+        kmc_run_until(self.h, t_end, max_events, buf)
+        return buf
+
     def clusters(self, species: int = 1, max_size: int = 64):
         """Device int64[max_size + 1] cluster-size histogram of `species`."""
         import torch
@@ -487,6 +570,31 @@ class Lattice:
         slots = np.empty(max(self.n_vac, 1), dtype=np.int32)
         s = state_read(self.h, occ, slots)
         return occ, slots[:self.n_vac], s
+
+
+class PatchNetBlob:
+    """A local patch network in device memory (akmc_patchnet_set layout):
+    policy (n_out = 8) or Poisson network (n_out = 1)."""
+
+    def __init__(self, S: int, H: int, n_out: int, device="cuda"):
+        import torch
+        self.S, self.H, self.n_out = int(S), int(H), int(n_out)
+        self.blob = torch.zeros(patchnet_blob_bytes(S, H, n_out), dtype=torch.uint8, device=device)
+
+    def set(self, w1, b1, w2, b2, w3, b3):
+        """w1 [64][S][H], b1 [H], w2 [H][H], b2 [H], w3 [H][n_out], b3 [n_out]."""
+        flat = np.concatenate([np.asarray(a, dtype=np.float32).ravel() for a in (w1, b1, w2, b2, w3, b3)])
+        patchnet_set(self.blob, self.S, self.H, self.n_out, flat)
+
+    def get(self):
+        """The stored (bfloat16-rounded) parameters as the six arrays."""
+        S, H, no, v = patchnet_get(self.blob)
+        out, o = [], 0
+        for shape in ((64, S, H), (H,), (H, H), (H,), (H, no), (no,)):
+            n = int(np.prod(shape))
+            out.append(v[o:o + n].reshape(shape).copy())
+            o += n
+        return out
 
 
 def log_to_numpy(buf, n: int) -> np.ndarray:

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libakmc.so")
-SOURCES = ["akmc_capi.hip", "akmc_rates.hip", "akmc_loop.hip", "akmc_mlp.hip", "akmc_cluster.hip"]
+SOURCES = ["akmc_capi.hip", "akmc_rates.hip", "akmc_loop.hip", "akmc_mlp.hip", "akmc_cluster.hip",
+           "akmc_voxels.hip", "akmc_patch.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

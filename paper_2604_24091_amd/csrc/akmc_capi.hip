@@ -14,6 +14,7 @@
 
 #include "akmc_internal.hpp"
 #include "akmc_mlp.hpp"
+#include "akmc_patch.hpp"
 
 using namespace akmc;
 
@@ -219,6 +220,10 @@ struct akmc_lattice {
   const unsigned char *mlp_blob = nullptr;
   LaunchTiming timing;  // events recorded by ALL_SITES launches (akmc_rates_timing)
   int device = 0;       // device current at create (where the workspace lives)
+  // learned runtime forms (akmc_policy_attach, akmc_poisson_attach)
+  const unsigned char *pol_blob = nullptr, *pt_blob = nullptr;
+  int pol_dims[3] = {0, 0, 0}, pt_dims[3] = {0, 0, 0};
+  float inv_tau = 1.0f;
 };
 
 extern "C" {
@@ -331,11 +336,26 @@ akmc_status akmc_rates_timing(akmc_handle h, void *start_event, void *stop_event
   return AKMC_OK;
 }
 
+static akmc_status run_loop(akmc_handle h, int64_t n_events, double t_end, akmc_event *d_log);
+
 akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log) {
   if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
   if (n_events < 0) return fail(AKMC_ERR_INVALID, "n_events must be >= 0");
   if (n_events == 0) return AKMC_OK;
   if (h->nv == 0) return fail(AKMC_ERR_FROZEN, "lattice has no vacancies");
+  return run_loop(h, n_events, HUGE_VAL, d_log);
+}
+
+akmc_status akmc_kmc_run_until(akmc_handle h, double t_end, int64_t max_events, akmc_event *d_log) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (max_events < 0) return fail(AKMC_ERR_INVALID, "max_events must be >= 0");
+  if (std::isnan(t_end)) return fail(AKMC_ERR_INVALID, "t_end is NaN");
+  if (max_events == 0) return AKMC_OK;
+  if (h->nv == 0) return fail(AKMC_ERR_FROZEN, "lattice has no vacancies");
+  return run_loop(h, max_events, t_end, d_log);
+}
+
+static akmc_status run_loop(akmc_handle h, int64_t n_events, double t_end, akmc_event *d_log) {
   LoopArgs a;
   std::memset(&a, 0, sizeof(a));
   a.descs = h->d_desc;
@@ -350,6 +370,20 @@ akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log) {
   if (mlp && !h->mlp_blob) return fail(AKMC_ERR_INVALID, "barrier_model MLP: attach weights with akmc_mlp_attach first");
   a.mlp_blob = h->mlp_blob;
   a.ea_trace = h->d_trace;
+  a.t_end = t_end;
+  const bool lrn = h->pol_blob || h->pt_blob;
+  if (lrn && mlp) return fail(AKMC_ERR_UNSUPPORTED, "the learned runtime forms use the pair barrier model");
+  a.pol_blob = h->pol_blob;
+  a.pt_blob = h->pt_blob;
+  a.inv_tau = h->inv_tau;
+  size_t lrn_lds = 0;
+  if (lrn) {
+    lrn_lds = event_loop_lrn_lds_bytes(h->nv, h->p.precision, h->pol_blob ? h->pol_dims : nullptr,
+                                       h->pt_blob ? h->pt_dims : nullptr);
+    if (lrn_lds > kLdsBytes)
+      return fail(AKMC_ERR_UNSUPPORTED, "the vacancies' rate tree and the attached networks exceed the "
+                                        "160 KiB of LDS of a workgroup");
+  }
   Schedule s{64, 1, 1};
   for (int64_t done = 0; done < n_events; done += kChunkEvents) {
     const int64_t n = std::min(kChunkEvents, n_events - done);
@@ -357,8 +391,9 @@ akmc_status akmc_kmc_step(akmc_handle h, int64_t n_events, akmc_event *d_log) {
     a.log = d_log ? d_log + done : nullptr;
     a.log_stride = n;
     const int full = h->p.refresh == AKMC_REFRESH_FULL;
-    hipError_t e = mlp ? launch_event_loop_mlp(a, full, h->p.n_species, h->stream)
-                       : launch_event_loop(a, h->p.precision, full, s, h->stream);
+    hipError_t e = lrn  ? launch_event_loop_lrn(a, h->p.precision, full, lrn_lds, h->stream)
+                   : mlp ? launch_event_loop_mlp(a, full, h->p.n_species, h->stream)
+                         : launch_event_loop(a, h->p.precision, full, s, h->stream);
     if (e != hipSuccess) return hip_fail(e, "kmc_step launch");
     h->stepped = true;
   }
@@ -542,6 +577,10 @@ struct akmc_batch_s {
   int32_t *d_order, *d_queue, *d_slots;
   double *d_scratch;
   uint8_t *d_occ;
+  void *d_trace;                      // barriers the loop last evaluated, [slots][8]
+  double *d_w;                        // workload proxy of every replica (Eq. 10)
+  bool stepped = false;               // a launch has filled d_trace
+  std::vector<int32_t> create_order;  // dispatch order chosen at create
   akmc_schedule sched;
   hipStream_t cap_stream = nullptr;   // capture-only stream (the legacy stream cannot capture)
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
@@ -550,7 +589,7 @@ struct akmc_batch_s {
 namespace {
 
 struct BatchLayout {
-  size_t descs, states, order, queue, slots, scratch, occ, total;
+  size_t descs, states, order, queue, slots, scratch, trace, w, occ, total;
   std::vector<int64_t> occ_off, slot_off;
 };
 
@@ -569,6 +608,8 @@ BatchLayout batch_layout(int n_rep, const akmc_params *p, const int32_t *n_vac) 
   }
   b.slots = o;   o += up(sizeof(int32_t) * (size_t)std::max<int64_t>(ns, 1));
   b.scratch = o; o += up(sizeof(double) * 24 * (size_t)nvmax);
+  b.trace = o;   o += up(sizeof(double) * 8 * (size_t)std::max<int64_t>(ns, 1));
+  b.w = o;       o += up(sizeof(double) * (size_t)n_rep);
   b.occ = o;
   int64_t oo = 0;
   for (int r = 0; r < n_rep; ++r) {
@@ -609,27 +650,34 @@ LoopArgs batch_args(const akmc_batch_s *b, int64_t n) {
   a.n_lat = b->n_rep;
   a.nv_max = b->nv_max;
   a.n_events = n;
+  a.t_end = HUGE_VAL;
+  a.ea_trace = b->d_trace;
   return a;
 }
 
-akmc_status batch_launch(akmc_batch_s *b, int64_t n, hipStream_t stream) {
+akmc_status batch_launch(akmc_batch_s *b, int64_t n, hipStream_t stream, double t_end = HUGE_VAL) {
   const Schedule s{b->sched.group_lanes, b->sched.waves_per_block, b->sched.blocks};
-  hipError_t e = launch_event_loop(batch_args(b, n), b->precision, b->refresh_full, s, stream);
+  LoopArgs a = batch_args(b, n);
+  a.t_end = t_end;
+  hipError_t e = launch_event_loop(a, b->precision, b->refresh_full, s, stream);
   if (e != hipSuccess) return hip_fail(e, "batch launch");
+  b->stepped = true;
   return AKMC_OK;
 }
 
 // One chunk as a graph: [queue reset, persistent loop], captured once per
-// (chunk, schedule) on the library's capture stream and replayed on the
-// caller's stream.
-akmc_status batch_graph_launch(akmc_batch_s *b, int64_t n) {
-  std::vector<int64_t> key{n, b->sched.group_lanes, b->sched.waves_per_block, b->sched.blocks};
+// (chunk, schedule, horizon) on the library's capture stream and replayed
+// on the caller's stream.
+akmc_status batch_graph_launch(akmc_batch_s *b, int64_t n, double t_end = HUGE_VAL) {
+  int64_t tbits;
+  std::memcpy(&tbits, &t_end, sizeof(tbits));
+  std::vector<int64_t> key{n, b->sched.group_lanes, b->sched.waves_per_block, b->sched.blocks, tbits};
   auto it = b->graphs.find(key);
   if (it == b->graphs.end()) {
     if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
-    akmc_status st = batch_launch(b, n, b->cap_stream);
+    akmc_status st = batch_launch(b, n, b->cap_stream, t_end);
     hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
     if (st != AKMC_OK) {
       if (graph) hipGraphDestroy(graph);
@@ -643,6 +691,7 @@ akmc_status batch_graph_launch(akmc_batch_s *b, int64_t n) {
     it = b->graphs.emplace(key, exec).first;
   }
   HIP_TRY(hipGraphLaunch(it->second, b->stream));
+  b->stepped = true;
   return AKMC_OK;
 }
 
@@ -703,6 +752,8 @@ akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p, const uint8_t
   b->d_queue = (int32_t *)(b->ws + lay.queue);
   b->d_slots = (int32_t *)(b->ws + lay.slots);
   b->d_scratch = (double *)(b->ws + lay.scratch);
+  b->d_trace = b->ws + lay.trace;
+  b->d_w = (double *)(b->ws + lay.w);
   b->d_occ = b->ws + lay.occ;
   // 8 lanes per replica, or the fewest lanes whose groups fit in LDS (64
   // lanes always fit: one group per wavefront).
@@ -733,6 +784,7 @@ akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p, const uint8_t
   }
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t x, int32_t y) { return weight[x] > weight[y]; });
+  b->create_order = order;
   hipError_t e = hipSuccess;
   const hipStream_t st = b->stream;
   if (e == hipSuccess) e = hipMemcpyAsync(b->d_descs, b->h_descs.data(), sizeof(LatDesc) * n_rep, hipMemcpyHostToDevice, st);
@@ -828,6 +880,53 @@ akmc_status akmc_batch_state_read(akmc_batch b, int32_t r, uint8_t *occ_host,
   return read_state(b->stream, b->d_descs + r, d, b->d_states + r, b->d_occ + d.occ_off,
                     b->d_slots + d.slot_off, b->d_scratch, b->nv[r], b->nsites[r], b->precision,
                     occ_host, slot_sites_host, out);
+}
+
+akmc_status akmc_batch_priority(akmc_batch b, double *d_w_out, int32_t *d_order_out) {
+  if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
+  if (!b->stepped) {
+    // A launch with no events evaluates every candidate and fills the trace.
+    akmc_status st = batch_launch(b, 0, b->stream);
+    if (st != AKMC_OK) return st;
+  }
+  hipError_t e = launch_priority(b->d_descs, b->d_trace, b->precision == AKMC_FP32, b->n_rep, b->d_w,
+                                 b->d_order, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "batch priority launch");
+  if (d_w_out)
+    HIP_TRY(hipMemcpyAsync(d_w_out, b->d_w, sizeof(double) * b->n_rep, hipMemcpyDeviceToDevice, b->stream));
+  if (d_order_out)
+    HIP_TRY(hipMemcpyAsync(d_order_out, b->d_order, sizeof(int32_t) * b->n_rep, hipMemcpyDeviceToDevice,
+                           b->stream));
+  return AKMC_OK;
+}
+
+akmc_status akmc_batch_run_until(akmc_batch b, double t_end, int64_t max_events_per_replica,
+                                 int32_t order) {
+  if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
+  if (std::isnan(t_end)) return fail(AKMC_ERR_INVALID, "t_end is NaN");
+  if (max_events_per_replica < 0) return fail(AKMC_ERR_INVALID, "max_events_per_replica must be >= 0");
+  if (order == AKMC_ORDER_PRIORITY) {
+    akmc_status st = akmc_batch_priority(b, nullptr, nullptr);
+    if (st != AKMC_OK) return st;
+  } else if (order == AKMC_ORDER_INDEX) {
+    hipError_t e = launch_order_index(b->d_order, b->n_rep, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "order launch");
+  } else if (order == AKMC_ORDER_CREATE) {
+    HIP_TRY(hipMemcpyAsync(b->d_order, b->create_order.data(), sizeof(int32_t) * b->n_rep,
+                           hipMemcpyHostToDevice, b->stream));
+  } else {
+    return fail(AKMC_ERR_INVALID, "order must be AKMC_ORDER_PRIORITY, _INDEX or _CREATE");
+  }
+  int64_t done = 0;
+  const int64_t chunk = std::min<int64_t>(b->sched.chunk_events, kChunkEvents);
+  while (done < max_events_per_replica) {
+    const int64_t n = std::min(chunk, max_events_per_replica - done);
+    akmc_status st = b->sched.use_graph ? batch_graph_launch(b, n, t_end)
+                                        : batch_launch(b, n, b->stream, t_end);
+    if (st != AKMC_OK) return st;
+    done += n;
+  }
+  return AKMC_OK;
 }
 
 akmc_status akmc_batch_destroy(akmc_batch b) {
@@ -1053,6 +1152,165 @@ akmc_status akmc_mlp_grad(const void *d_blob, int32_t n_species, const uint8_t *
                                  (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "mlp_grad launch");
   return AKMC_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------- voxel ensemble
+
+extern "C" {
+
+akmc_status akmc_voxel_grid(const double *T, int32_t nx, int32_t nz, double e_eff, double kb,
+                            double tol, int32_t *n_x, int32_t *n_z, double *t_vox, double *worst) {
+  if (!T || !n_x || !n_z || !t_vox) return fail(AKMC_ERR_INVALID, "NULL argument");
+  if (nx < 1 || nz < 1) return fail(AKMC_ERR_INVALID, "nx and nz must be >= 1");
+  if (!(e_eff > 0.0) || !(kb > 0.0) || !(tol > 0.0) || !std::isfinite(e_eff) || !std::isfinite(kb) ||
+      !std::isfinite(tol))
+    return fail(AKMC_ERR_INVALID, "e_eff, kb and tol must be finite and > 0");
+  for (int64_t q = 0; q < (int64_t)nx * nz; ++q)
+    if (!(T[q] > 0.0) || !std::isfinite(T[q]))
+      return fail(AKMC_ERR_INVALID, "temperature samples must be finite and > 0");
+  int gx = 0, gz = 0;
+  double w = 0.0;
+  if (voxel_grid(T, nx, nz, e_eff, kb, tol, &gx, &gz, t_vox, &w) != 0)
+    return fail(AKMC_ERR_INVALID, "no voxel grid meets the tolerance");
+  *n_x = gx;
+  *n_z = gz;
+  if (worst) *worst = w;
+  return AKMC_OK;
+}
+
+// ------------------------------------------------ learned runtime forms
+
+akmc_status akmc_patchnet_blob_bytes(int32_t n_species, int32_t hidden, int32_t n_out, size_t *bytes) {
+  if (n_species < 2 || n_species > AKMC_MAX_SPECIES) return fail(AKMC_ERR_INVALID, "n_species must lie in [2, 8]");
+  if (hidden < 1 || hidden > kPatchMaxHidden) return fail(AKMC_ERR_INVALID, "hidden must lie in [1, 64]");
+  if (n_out != 1 && n_out != 8) return fail(AKMC_ERR_INVALID, "n_out must be 1 (Poisson) or 8 (policy)");
+  if (!bytes) return fail(AKMC_ERR_INVALID, "bytes is NULL");
+  *bytes = patch_layout(n_species, hidden, n_out).total;
+  return AKMC_OK;
+}
+
+static float round_bf16(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;   // to nearest, ties to even
+  float y;
+  std::memcpy(&y, &u, 4);
+  return y;
+}
+
+akmc_status akmc_patchnet_set(void *d_blob, int32_t n_species, int32_t hidden, int32_t n_out,
+                              const float *host_params) {
+  size_t bytes = 0;
+  akmc_status st = akmc_patchnet_blob_bytes(n_species, hidden, n_out, &bytes);
+  if (st != AKMC_OK) return st;
+  if (!d_blob || !host_params) return fail(AKMC_ERR_INVALID, "NULL blob or parameters");
+  if (!aligned(d_blob)) return fail(AKMC_ERR_INVALID, "blob must be 256-byte aligned");
+  const PatchLayout L = patch_layout(n_species, hidden, n_out);
+  std::vector<unsigned char> img(L.total, 0);
+  PatchHeader hdr{};
+  hdr.S = n_species;
+  hdr.H = hidden;
+  hdr.n_out = n_out;
+  hdr.nparams = L.nparams;
+  hdr.magic = kPatchMagic;
+  std::memcpy(img.data(), &hdr, sizeof(hdr));
+  float *p = reinterpret_cast<float *>(img.data() + L.params);
+  for (int x = 0; x < L.nparams; ++x) {
+    const float v = host_params[x];
+    if (!std::isfinite(v)) return fail(AKMC_ERR_INVALID, "parameters must be finite");
+    const bool bias = (x >= L.ob1 && x < L.oW2) || (x >= L.ob2 && x < L.oW3) || x >= L.ob3;
+    p[x] = bias ? v : round_bf16(v);
+    if (!std::isfinite(p[x])) return fail(AKMC_ERR_INVALID, "a weight overflows bfloat16");
+  }
+  HIP_TRY(hipMemcpy(d_blob, img.data(), L.total, hipMemcpyHostToDevice));
+  return AKMC_OK;
+}
+
+static akmc_status read_patch_header(const void *d_blob, PatchHeader *hdr) {
+  if (!d_blob) return fail(AKMC_ERR_INVALID, "blob is NULL");
+  HIP_TRY(hipMemcpy(hdr, d_blob, sizeof(PatchHeader), hipMemcpyDeviceToHost));
+  if (hdr->magic != kPatchMagic || hdr->S < 2 || hdr->S > AKMC_MAX_SPECIES || hdr->H < 1 ||
+      hdr->H > kPatchMaxHidden || (hdr->n_out != 1 && hdr->n_out != 8))
+    return fail(AKMC_ERR_INVALID, "not a network blob written by akmc_patchnet_set");
+  return AKMC_OK;
+}
+
+akmc_status akmc_patchnet_get(const void *d_blob, int32_t *n_species, int32_t *hidden, int32_t *n_out,
+                              float *host_params) {
+  PatchHeader hdr;
+  akmc_status st = read_patch_header(d_blob, &hdr);
+  if (st != AKMC_OK) return st;
+  if (n_species) *n_species = hdr.S;
+  if (hidden) *hidden = hdr.H;
+  if (n_out) *n_out = hdr.n_out;
+  if (host_params) {
+    const PatchLayout L = patch_layout(hdr.S, hdr.H, hdr.n_out);
+    HIP_TRY(hipMemcpy(host_params, static_cast<const unsigned char *>(d_blob) + L.params,
+                      sizeof(float) * (size_t)L.nparams, hipMemcpyDeviceToHost));
+  }
+  return AKMC_OK;
+}
+
+akmc_status akmc_patchnet_eval(akmc_handle h, const void *d_blob, const int32_t *d_sites,
+                               int64_t n_sites, float *d_out) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (n_sites < 0) return fail(AKMC_ERR_INVALID, "n_sites must be >= 0");
+  if (n_sites > 0 && (!d_sites || !d_out)) return fail(AKMC_ERR_INVALID, "NULL sites or output");
+  PatchHeader hdr;
+  akmc_status st = read_patch_header(d_blob, &hdr);
+  if (st != AKMC_OK) return st;
+  if (hdr.S != h->p.n_species) return fail(AKMC_ERR_INVALID, "network species count differs from the lattice's");
+  if (h->p.lx < 5 || h->p.ly < 5 || h->p.lz < 5)
+    return fail(AKMC_ERR_INVALID, "the 64-neighbour observation needs lattice edges of at least 5 cells");
+  hipError_t e = launch_patch_eval(h->d_desc, h->d_occ, static_cast<const unsigned char *>(d_blob), hdr.S,
+                                   hdr.H, hdr.n_out, d_sites, n_sites, d_out, h->stream);
+  if (e != hipSuccess) return hip_fail(e, "patchnet_eval launch");
+  return AKMC_OK;
+}
+
+static akmc_status attach_net(akmc_handle h, const void *d_blob, int want_out, const unsigned char **slot,
+                              int (&dims)[3]) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (!d_blob) {
+    *slot = nullptr;
+    return AKMC_OK;
+  }
+  PatchHeader hdr;
+  akmc_status st = read_patch_header(d_blob, &hdr);
+  if (st != AKMC_OK) return st;
+  if (hdr.n_out != want_out)
+    return fail(AKMC_ERR_INVALID, want_out == 8 ? "a policy blob has 8 outputs" : "a Poisson blob has 1 output");
+  if (hdr.S != h->p.n_species) return fail(AKMC_ERR_INVALID, "network species count differs from the lattice's");
+  if (h->p.lx < 5 || h->p.ly < 5 || h->p.lz < 5)
+    return fail(AKMC_ERR_INVALID, "the 64-neighbour observation needs lattice edges of at least 5 cells");
+  if (h->p.barrier_model != AKMC_BARRIER_PAIR)
+    return fail(AKMC_ERR_UNSUPPORTED, "the learned runtime forms use the pair barrier model");
+  const int d[3] = {hdr.S, hdr.H, hdr.n_out};
+  const unsigned char *pol = want_out == 8 ? static_cast<const unsigned char *>(d_blob) : h->pol_blob;
+  const unsigned char *pt = want_out == 1 ? static_cast<const unsigned char *>(d_blob) : h->pt_blob;
+  const size_t lds = event_loop_lrn_lds_bytes(h->nv, h->p.precision, pol ? (want_out == 8 ? d : h->pol_dims) : nullptr,
+                                              pt ? (want_out == 1 ? d : h->pt_dims) : nullptr);
+  if (lds > kLdsBytes)
+    return fail(AKMC_ERR_UNSUPPORTED, "the vacancies' rate tree and the attached networks exceed the 160 KiB "
+                                      "of LDS of a workgroup");
+  *slot = static_cast<const unsigned char *>(d_blob);
+  for (int q = 0; q < 3; ++q) dims[q] = d[q];
+  return AKMC_OK;
+}
+
+akmc_status akmc_policy_attach(akmc_handle h, const void *d_blob, float tau) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  if (d_blob && !(tau > 0.0f && std::isfinite(tau))) return fail(AKMC_ERR_INVALID, "tau must be finite and > 0");
+  akmc_status st = attach_net(h, d_blob, 8, &h->pol_blob, h->pol_dims);
+  if (st == AKMC_OK && d_blob) h->inv_tau = 1.0f / tau;
+  return st;
+}
+
+akmc_status akmc_poisson_attach(akmc_handle h, const void *d_blob) {
+  if (!h) return fail(AKMC_ERR_INVALID, "handle is NULL");
+  return attach_net(h, d_blob, 1, &h->pt_blob, h->pt_dims);
 }
 
 }  // extern "C"

@@ -82,6 +82,14 @@ struct LoopArgs {
   // precision (double, or float for binary32): after every event it holds
   // the barriers of the current state (+inf for an inadmissible jump).
   void *ea_trace;
+  // Time horizon: an event starts only while the lattice's t < t_end
+  // (+inf for a fixed number of events).
+  double t_end;
+  // Learned runtime forms (launch_event_loop_lrn only): local policy
+  // network choosing the events (NULL: the rates choose) with logits scaled
+  // by inv_tau, Poisson time network (NULL: time_mode).
+  const unsigned char *pol_blob, *pt_blob;
+  float inv_tau;
 };
 
 // LDS carve-up of one lattice group in the event loop.  Every array is
@@ -147,6 +155,25 @@ hipError_t launch_event_loop(const LoopArgs &a, int precision, int refresh_full,
 hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_species,
                                  hipStream_t stream);
 size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision);
+// Event loop with the learned runtime forms (one 64-lane group); lds from
+// event_loop_lrn_lds_bytes with each attached network's (S, H, n_out).
+hipError_t launch_event_loop_lrn(const LoopArgs &a, int precision, int refresh_full, size_t lds,
+                                 hipStream_t stream);
+size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3],
+                                const int pt_dims[3]);
+// Local patch networks on listed sites: out[n][n_out] (NaN for a site
+// outside the lattice).
+hipError_t launch_patch_eval(const LatDesc *d_desc, const uint8_t *d_occ, const unsigned char *d_blob,
+                             int S, int H, int n_out, const int32_t *d_sites, int64_t n, float *d_out,
+                             hipStream_t st);
+size_t patch_eval_lds_bytes(int S, int H, int n_out);
+// Voxel ensembles: the discretisation of a thermal field (host), and the
+// workload proxy of every replica with the heaviest-first order (device).
+int voxel_grid(const double *T, int nx, int nz, double e_eff, double kb, double tol, int *n_x,
+               int *n_z, double *t_vox, double *worst);
+hipError_t launch_priority(const LatDesc *d_descs, const void *d_trace, int fp32, int n_rep,
+                           double *d_w, int32_t *d_order, hipStream_t st);
+hipError_t launch_order_index(int32_t *d_order, int n_rep, hipStream_t st);
 // LDS of the event loop with the learned barrier (one 64-lane group).
 size_t event_loop_mlp_lds_bytes(int nv_max, int n_species);
 // LDS a workgroup may hold on gfx950.

@@ -28,6 +28,7 @@
 #include "akmc_device.hpp"
 #include "akmc_internal.hpp"
 #include "akmc_mlp.hpp"
+#include "akmc_patch.hpp"
 
 namespace akmc {
 
@@ -71,6 +72,45 @@ __constant__ FootTab kFoot = make_foot();
 
 constexpr int kFootN = 59;       // 58 gathered sites + the vacancy itself
 constexpr int kBoxC = 3 + 7 * 3 + 49 * 3;
+// With the learned runtime forms a vacancy's 64-neighbour observation also
+// needs the 6 sites 4 half-cells away along an axis, outside the 7x7x7 box:
+// they are gathered with the footprint and kept in box bytes kFarOff.. of
+// their box, in the order (-x, -y, -z, +z, +y, +x) of the observation.
+constexpr int kFootNL = kFootN + 6;
+constexpr int kFarOff = 344;
+static_assert(kFarOff >= 343 && kFarOff + 6 <= kBoxBytes, "far sites fit the box padding");
+constexpr int kFarD[6][3] = {{-4, 0, 0}, {0, -4, 0}, {0, 0, -4}, {0, 0, 4}, {0, 4, 0}, {4, 0, 0}};
+
+// Packed gather element: box byte (bits 0-8; the index 0..5 of a far site),
+// offsets + 4 (bits 9-12, 13-16, 17-20), box number q (bits 21-26), centre
+// flag (bit 27), far flag (bit 28); -1 for none.
+__device__ __forceinline__ int fe_dx(int f) { return ((f >> 9) & 15) - 4; }
+__device__ __forceinline__ int fe_dy(int f) { return ((f >> 13) & 15) - 4; }
+__device__ __forceinline__ int fe_dz(int f) { return ((f >> 17) & 15) - 4; }
+__device__ __forceinline__ int fe_q(int f) { return (f >> 21) & 63; }
+__device__ __forceinline__ bool fe_centre(int f) { return (f >> 27) & 1; }
+__device__ __forceinline__ int fe_byte(int f) { return ((f >> 28) & 1) ? kFarOff + (f & 511) : (f & 511); }
+
+// Box byte of each observation neighbour: inside the 7x7x7 box, or the far
+// slot of an axis site 4 half-cells away.
+struct ObsSrc {
+  int16_t b[kObsN];
+};
+constexpr ObsSrc make_obs_src() {
+  ObsSrc r{};
+  const ObsTab t = make_obs();
+  for (int m = 0; m < kObsN; ++m) {
+    const int dx = t.d[m][0], dy = t.d[m][1], dz = t.d[m][2];
+    int src = -1;
+    for (int f = 0; f < 6; ++f)
+      if (kFarD[f][0] == dx && kFarD[f][1] == dy && kFarD[f][2] == dz) src = kFarOff + f;
+    if (src < 0) src = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
+    r.b[m] = (int16_t)src;
+  }
+  return r;
+}
+constexpr ObsSrc kObsSrcHost = make_obs_src();
+__constant__ ObsSrc kObsSrc = make_obs_src();
 
 template <int G>
 struct Group {
@@ -181,11 +221,15 @@ __host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
 
 // KL: the most tree levels of any lattice of the launch (at most
 // kMaxLevels); the level loops are unrolled that far.
-template <int G, class Real, bool MLP = false, int KL = kMaxLevels>
+// LRN: the learned runtime forms (policy selection, Poisson time), one
+// 64-lane group per launch.
+template <int G, class Real, bool MLP = false, int KL = kMaxLevels, bool LRN = false>
 struct Runner {
+  static constexpr int FN = LRN ? kFootNL : kFootN;  // gather elements per box
+  static constexpr int FM = LRN ? 9 : 8;             // gather elements per lane and pass
   LoopArgs a;
   Group<G> gp;
-  int foot[8];
+  int foot[FM];
   Lds<Real> s;
   Geo g;
   int S, V, nv, nlev;
@@ -204,12 +248,40 @@ struct Runner {
   uint32_t oodw[4], seen;
   double top_q;   // lane c < 8: partial c of the top tree level (cached between events)
   Real *eat;      // barrier trace of this lattice (LoopArgs::ea_trace) or NULL
+  // learned runtime forms
+  bool has_pol, has_pt;
+  float inv_tau;
+  PatchNet pol, pt;
+  double *pg;     // [nv] total pair rate of each slot (policy selection)
+  double *gv;     // [nv] Poisson network value of each slot
+  double *wq;     // [64] selection weights of one refresh pass, lane order
+  uint8_t *obs;   // [8][64] observation codes of one refresh pass
+  float *hbuf;    // [64] activation staging
 
   __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
-                    const int (&foot_)[8], unsigned char *lds)
+                    const int (&foot_)[FM], unsigned char *lds)
       : a(a_), gp(gp_) {
     s = carve<Real>(lds, L);
     n_ood = 0;
+    has_pol = has_pt = false;
+    if (LRN) {
+      unsigned char *b = lds + L.bytes;
+      pg = (double *)b;
+      gv = pg + a.nv_max;
+      wq = gv + a.nv_max;
+      hbuf = (float *)(wq + 64);
+      obs = (uint8_t *)(hbuf + 64);
+      b = obs + 8 * kObsN;
+      has_pol = a.pol_blob != nullptr;
+      has_pt = a.pt_blob != nullptr;
+      inv_tau = a.inv_tau;
+      if (has_pol) {
+        pol = patch_stage(a.pol_blob, b, gp.gl, G);
+        b += patch_lds_bytes(pol.S, pol.H, pol.n_out);
+      }
+      if (has_pt) pt = patch_stage(a.pt_blob, b, gp.gl, G);
+      gsync();
+    }
     if (MLP) {
       const MlpHeader *hdr = (const MlpHeader *)a.mlp_blob;
       const int Sm = hdr->S;
@@ -255,7 +327,7 @@ struct Runner {
       gsync();
     }
 #pragma unroll
-    for (int m = 0; m < 8; ++m) foot[m] = foot_[m];
+    for (int m = 0; m < FM; ++m) foot[m] = foot_[m];
   }
 
   // Level l (1-based) of the tree: its nodes and their count.  Level m of
@@ -443,18 +515,18 @@ struct Runner {
     constexpr int P = G / 8;
     for (int p0 = 0; p0 < na; p0 += P) {
       const int np = min(P, na - p0);
-      int site[8];
-      uint8_t val[8];
+      int site[FM];
+      uint8_t val[FM];
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
+      for (int m = 0; m < FM; ++m) {
         const int f = foot[m];
         site[m] = -1;
         val[m] = (uint8_t)V;
-        if (f < 0 || ((f >> 18) & 63) >= np || (f & (1 << 24))) continue;
-        const int pp = s.pos[s.aff[p0 + ((f >> 18) & 63)]];
-        const int X = wrapc(pos_x(pp) + ((f >> 9) & 7) - 3, g.X2);
-        const int Y = wrapc(pos_y(pp) + ((f >> 12) & 7) - 3, g.Y2);
-        const int Z = wrapc(pos_z(pp) + ((f >> 15) & 7) - 3, g.Z2);
+        if (f < 0 || fe_q(f) >= np || fe_centre(f)) continue;
+        const int pp = s.pos[s.aff[p0 + fe_q(f)]];
+        const int X = wrapc(pos_x(pp) + fe_dx(f), g.X2);
+        const int Y = wrapc(pos_y(pp) + fe_dy(f), g.Y2);
+        const int Z = wrapc(pos_z(pp) + fe_dz(f), g.Z2);
         site[m] = site_of(g, X, Y, Z);
         val[m] = occ[site[m]];
       }
@@ -464,13 +536,13 @@ struct Runner {
         if (ev) *ev = rec;
       }
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
+      for (int m = 0; m < FM; ++m) {
         const int f = foot[m];
-        if (f < 0 || ((f >> 18) & 63) >= np) continue;
+        if (f < 0 || fe_q(f) >= np) continue;
         uint8_t v8 = val[m];
         if (site[m] == si) v8 = (uint8_t)a_new;
         else if (site[m] == sj) v8 = (uint8_t)V;
-        s.box[((f >> 18) & 63) * kBoxBytes + (f & 511)] = (uint8_t)(v8 << 2);
+        s.box[fe_q(f) * kBoxBytes + fe_byte(f)] = (uint8_t)(v8 << 2);
       }
       gsync();
       const int q = gp.gl >> 3, k = gp.gl & 7;
@@ -488,11 +560,42 @@ struct Runner {
       } else {
         r = eval_mlp_pass(np, q, k, p0, vv);
       }
+      if (LRN) r = learned_pass(np, p0, q, k, r, vv);
       // part[v][k] = r0 + r1 + ... + rk
       const double acc = subgroup_prefix(r, k);
       if (q < np) s.part[vv * 8 + k] = acc;
       gsync();
     }
+  }
+
+  // Learned runtime forms for the np slots aff[p0 ..] of one refresh pass
+  // whose boxes are gathered (lane q*8+k holds the pair rate r of candidate
+  // k of pass slot q, vv that slot): stores each slot's total pair rate and
+  // Poisson value, and returns the weight the selection uses for this
+  // lane's candidate (the policy's exp(z_hat), or r).
+  __device__ double learned_pass(int np, int p0, int q, int k, double r, int vv) {
+    static_assert(!LRN || G == 64, "the learned forms run on one 64-lane group");
+    const int gl = gp.gl;
+    const double pfx = subgroup_prefix(r, k);
+    if (q < np && k == 7) pg[vv] = pfx;
+    for (int qq = 0; qq < np; ++qq) obs[qq * kObsN + gl] = s.box[qq * kBoxBytes + kObsSrc.b[gl]] >> 2;
+    gsync();
+    for (int qq = 0; qq < np; ++qq) {
+      const int v_q = s.aff[p0 + qq];
+      if (has_pol) {
+        const float z = patch_forward(pol, obs + qq * kObsN, hbuf, gl);
+        if (gl < 8) {
+          const bool ok = s.spec[v_q * 8 + gl] != (uint8_t)V;
+          wq[qq * 8 + gl] = ok ? exp((double)(z * inv_tau)) : 0.0;
+        }
+      }
+      if (has_pt) {
+        const float gval = patch_forward(pt, obs + qq * kObsN, hbuf, gl);
+        if (gl == 0) gv[v_q] = (double)gval;
+      }
+    }
+    gsync();
+    return has_pol ? (q < np ? wq[gl] : 0.0) : r;
   }
 
   // Distinct parents (index >> 3) of an ascending list.
@@ -549,6 +652,17 @@ struct Runner {
     return Q(nlev)[nl(nlev) - 1];
   }
 
+  // Sum of a per-slot array in an order fixed by nv alone: lane l adds
+  // slots l, l + 64, ... in turn, then a butterfly over the 64 lanes (every
+  // lane ends with the same value).  64-lane groups only.
+  __device__ double slot_sum(const double *x) const {
+    double acc = 0.0;
+    for (int v = gp.gl; v < nv; v += 64) acc += x[v];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    return acc;
+  }
+
   __device__ void run(int lat) {
     const LatDesc *d = a.descs + lat;
     LatState *st = a.states + lat;
@@ -594,10 +708,20 @@ struct Runner {
     refresh(nv, -1, -1, 0, false, nullptr, none);
     update_tree(nv);
     double gtot = gamma_tot();
-    frozen = !(gtot > 0.0);
+    // With the learned forms the tree holds the selection weights; the
+    // physical total rate (time) and u(s) are sums over the slots.
+    double gphys = gtot, uval = 0.0;
+    if (LRN) {
+      if (has_pol) gphys = slot_sum(pg);
+      if (has_pt) uval = slot_sum(gv);
+    }
+    frozen = !(gtot > 0.0) || !(gphys > 0.0);
 
     double ru1v = 0.0, rwv = 0.0;
-    for (int64_t e = 0; e < a.n_events && !frozen; ++e) {
+    // An event starts only while t < t_end (+inf unless the launch advances
+    // lattices to a physical-time horizon), so the event that reaches the
+    // horizon is the last one.
+    for (int64_t e = 0; e < a.n_events && !frozen && t < a.t_end; ++e) {
       const int ce = (int)(e % G);
       if (ce == 0) {
         double u1, u2;
@@ -700,7 +824,9 @@ struct Runner {
       const int JX = wrapc(X + dir_sx(k), g.X2), JY = wrapc(Y + dir_sy(k), g.Y2),
                 JZ = wrapc(Z + dir_sz(k), g.Z2);
       const int si = site_of(g, X, Y, Z), sj = site_of(g, JX, JY, JZ);
-      const double dt = time_mode ? 1.0 / gtot : w / gtot;
+      // Poisson time (Eq. 7) needs the state after the jump: its dt is set
+      // after the refresh.
+      double dt = time_mode ? 1.0 / gphys : w / gphys;
       akmc_event rec;
       rec.n = n;
       rec.slot = v;
@@ -710,16 +836,17 @@ struct Runner {
       rec.species = (uint8_t)A;
       rec.pad[0] = 0;
       rec.pad[1] = 0;
-      rec.gamma_tot = gtot;
+      rec.gamma_tot = gphys;
       rec.dt = dt;
       akmc_event *ev = evlog ? evlog + e : nullptr;
+      const bool late_rec = LRN && has_pt;   // the record waits for Eq. 7's dt
 
       // Stores of earlier events are complete before any gather.
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       // Footprint of the moved vacancy around its new site j, gathered
       // before the swap is stored; the two swapped sites are patched below.
       // Box 0 holds elements 0 .. kFootN-1, i.e. the first M0 of this lane.
-      constexpr int M0 = (kFootN + G - 1) / G;
+      constexpr int M0 = (FN + G - 1) / G;
       int site0[M0];
       uint8_t val0[M0];
 #pragma unroll
@@ -727,17 +854,17 @@ struct Runner {
         const int f = foot[m];
         site0[m] = -1;
         val0[m] = (uint8_t)V;
-        if (f < 0 || ((f >> 18) & 63) != 0 || (f & (1 << 24))) continue;
-        const int FX = wrapc(JX + ((f >> 9) & 7) - 3, g.X2);
-        const int FY = wrapc(JY + ((f >> 12) & 7) - 3, g.Y2);
-        const int FZ = wrapc(JZ + ((f >> 15) & 7) - 3, g.Z2);
+        if (f < 0 || fe_q(f) != 0 || fe_centre(f)) continue;
+        const int FX = wrapc(JX + fe_dx(f), g.X2);
+        const int FY = wrapc(JY + fe_dy(f), g.Y2);
+        const int FZ = wrapc(JZ + fe_dz(f), g.Z2);
         site0[m] = site_of(g, FX, FY, FZ);
         val0[m] = occ[site0[m]];
       }
       if (gl == 0) {
         occ[si] = (uint8_t)A;
         occ[sj] = (uint8_t)V;
-        if (ev) *ev = rec;
+        if (ev && !late_rec) *ev = rec;
       }
       if (gl == 0) s.pos[v] = pack_pos(JX, JY, JZ);
       gsync();
@@ -762,7 +889,10 @@ struct Runner {
             dx = min(dx, g.X2 - dx);
             dy = min(dy, g.Y2 - dy);
             dz = min(dz, g.Z2 - dz);
-            hit[u] = b0 + u * G + gl < nv && max(dx, max(dy, dz)) <= 4;
+            // reach: a candidate's bonds lie within 3 half-cells of its
+            // vacancy, an observation within 4, so i or j changes them only
+            // within 4 (5) half-cells of i
+            hit[u] = b0 + u * G + gl < nv && max(dx, max(dy, dz)) <= (LRN ? 5 : 4);
           }
         };
         bool others = false;
@@ -776,7 +906,7 @@ struct Runner {
         }
         if (!others) {
           na = 1;
-          if (MLP) {
+          if (MLP || LRN) {
             if (gl == 0) s.aff[0] = v;
             gsync();
           }
@@ -795,7 +925,7 @@ struct Runner {
           gsync();
         }
       }
-      t += dt;
+      if (!late_rec) t += dt;
       dig = fnv_event(dig, n, si, sj);
       n += 1;
 
@@ -804,12 +934,12 @@ struct Runner {
 #pragma unroll
         for (int m = 0; m < M0; ++m) {
           const int f = foot[m];
-          if (f < 0 || ((f >> 18) & 63) != 0) continue;
+          if (f < 0 || fe_q(f) != 0) continue;
           uint8_t v8 = val0[m];
-          if (f & (1 << 24)) v8 = (uint8_t)V;
+          if (fe_centre(f)) v8 = (uint8_t)V;
           else if (site0[m] == si) v8 = (uint8_t)A;
           else if (site0[m] == sj) v8 = (uint8_t)V;
-          s.box[f & 511] = (uint8_t)(v8 << 2);
+          s.box[fe_byte(f)] = (uint8_t)(v8 << 2);
         }
         gsync();
         const int kk = gl & 7;
@@ -821,6 +951,7 @@ struct Runner {
           s.spec[v * 8 + kk] = (uint8_t)Ak;
           if (eat) eat[v * 8 + kk] = ea;
         }
+        if (LRN) r = learned_pass(1, 0, gl >> 3, kk, r, v);
         const double pfx = subgroup_prefix(r, kk);
         if (gl < 8) s.part[v * 8 + kk] = pfx;
         gtot = update_path(v, lane_value(pfx, 7));
@@ -829,7 +960,21 @@ struct Runner {
         update_tree(na);
         gtot = gamma_tot();
       }
-      frozen = !(gtot > 0.0);
+      if (LRN) {
+        const double g_prev = gphys, u_prev = uval;
+        gphys = has_pol ? slot_sum(pg) : gtot;
+        if (has_pt) {
+          uval = slot_sum(gv);
+          // Eq. 7; a frozen successor drops its term (tau = 0 there)
+          dt = gphys > 0.0 ? (u_prev - (g_prev / gphys) * uval) / g_prev : u_prev / g_prev;
+          t += dt;
+          rec.dt = dt;
+          if (gl == 0 && ev) *ev = rec;
+        }
+      } else {
+        gphys = gtot;
+      }
+      frozen = !(gtot > 0.0) || !(gphys > 0.0);
     }
 
     for (int v = gl; v < nv; v += G) {
@@ -849,7 +994,7 @@ struct Runner {
   }
 };
 
-template <int G, int WAVES, bool FP32, bool MLP = false, int KL = kMaxLevels>
+template <int G, int WAVES, bool FP32, bool MLP = false, int KL = kMaxLevels, bool LRN = false>
 __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayout L) {
   using Real = typename std::conditional<FP32, float, double>::type;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -862,28 +1007,35 @@ __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayo
   unsigned char *mine = lds + (size_t)gib * L.bytes;
 
   // This lane's share of the footprint gathers: element f = gl + G*m of the
-  // (G/8) boxes of a refresh pass.  Packed: box index (9 bits), offsets + 3
-  // (3 x 3 bits), box number q (6 bits), centre flag (bit 24); -1 if none.
-  int foot[8];
+  // (G/8) boxes of a refresh pass, packed as described at fe_dx (box byte,
+  // offsets, box number q, centre and far flags); -1 if none.
+  using Run = Runner<G, Real, MLP, KL, LRN>;
+  constexpr int FN = Run::FN, FM = Run::FM;
+  int foot[FM];
   constexpr int P = G / 8;
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
+  for (int m = 0; m < FM; ++m) {
     const int f = gp.gl + G * m;
-    if (f >= P * kFootN) {
+    if (f >= P * FN) {
       foot[m] = -1;
       continue;
     }
-    const int q = f / kFootN, e = f % kFootN;
-    if (e == kFootN - 1) {
-      foot[m] = kBoxC | (q << 18) | (1 << 24);
+    const int q = f / FN, e = f % FN;
+    if (e == FN - 1) {
+      foot[m] = kBoxC | (4 << 9) | (4 << 13) | (4 << 17) | (q << 21) | (1 << 27);
+    } else if (e >= kFootN - 1) {
+      const int fi = e - (kFootN - 1);  // order of kFarD: -x, -y, -z, +z, +y, +x
+      const int axis = fi < 3 ? fi : 5 - fi, len = fi < 3 ? -4 : 4;
+      const int dx = axis == 0 ? len : 0, dy = axis == 1 ? len : 0, dz = axis == 2 ? len : 0;
+      foot[m] = fi | ((dx + 4) << 9) | ((dy + 4) << 13) | ((dz + 4) << 17) | (q << 21) | (1 << 28);
     } else {
       const int dx = kFoot.d[e][0], dy = kFoot.d[e][1], dz = kFoot.d[e][2];
       const int bi = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
-      foot[m] = bi | ((dx + 3) << 9) | ((dy + 3) << 12) | ((dz + 3) << 15) | (q << 18);
+      foot[m] = bi | ((dx + 4) << 9) | ((dy + 4) << 13) | ((dz + 4) << 17) | (q << 21);
     }
   }
 
-  Runner<G, Real, MLP, KL> run(a, L, gp, foot, mine);
+  Run run(a, L, gp, foot, mine);
   for (;;) {
     int idx = 0;
     if (gp.gl == 0) idx = atomicAdd(a.queue, 1);
@@ -962,6 +1114,36 @@ hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_spec
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(1), dim3(64), lds, stream, b, L);
   return hipGetLastError();
+}
+
+size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3],
+                                const int pt_dims[3]) {
+  const GroupLayout L = make_layout(nv_max, 64, precision == AKMC_FP32);
+  size_t b = (size_t)L.bytes + 16 * (size_t)nv_max + 8 * 64 + 4 * 64 + kObsN * 8;
+  if (pol_dims) b += (size_t)patch_lds_bytes(pol_dims[0], pol_dims[1], pol_dims[2]);
+  if (pt_dims) b += (size_t)patch_lds_bytes(pt_dims[0], pt_dims[1], pt_dims[2]);
+  return b;
+}
+
+template <bool FP32>
+static hipError_t launch_lrn(const LoopArgs &a, size_t lds, hipStream_t stream) {
+  const GroupLayout L = make_layout(a.nv_max, 64, FP32 ? 1 : 0);
+  auto kern = L.nlev_max <= 2 ? k_event_loop<64, 1, FP32, false, 2, true>
+                              : k_event_loop<64, 1, FP32, false, 3, true>;
+  hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(1), dim3(64), lds, stream, a, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_event_loop_lrn(const LoopArgs &a, int precision, int refresh_full, size_t lds,
+                                 hipStream_t stream) {
+  LoopArgs b = a;
+  b.refresh_full = refresh_full;
+  hipError_t e = launch_queue_reset(a.queue, stream);
+  if (e != hipSuccess) return e;
+  return precision == AKMC_FP32 ? launch_lrn<true>(b, lds, stream) : launch_lrn<false>(b, lds, stream);
 }
 
 hipError_t launch_event_loop(const LoopArgs &a, int precision, int refresh_full,

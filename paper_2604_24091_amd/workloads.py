@@ -163,6 +163,50 @@ def rpv_replicas(n_rep: int = 256, seed: int = 1003,
     return reps
 
 
+def wall_thermal_field(nx: int = 32, nz: int = 96, t_inlet: float = 533.0,
+                       t_outlet: float = 593.0, wall_drop: float = 10.0) -> np.ndarray:
+    """Temperature samples T[z][x] (K) over a section of a reactor-vessel
+    wall: x runs through the wall from the inner to the outer surface, z along
+    the axis over the core belt.  A stand-in for the CAP1400 service field of
+    Sec. IV-B, whose data the paper does not give: the inner surface follows
+    the coolant from inlet to outlet temperature along z (cosine heating
+    shape) and the wall cools linearly by wall_drop toward its outer surface,
+    which spans the 523-593 K range of the replica ensembles."""
+    x = (np.arange(nx) + 0.5) / nx
+    z = (np.arange(nz) + 0.5) / nz
+    tz = t_inlet + (t_outlet - t_inlet) * 0.5 * (1.0 - np.cos(np.pi * z))
+    return tz[:, None] - wall_drop * x[None, :]
+
+
+def voxel_replicas(temps: Sequence[float], n_x: int, n_z: int, cells: int = 16,
+                   seed: int = 1004, max_vac: int = 8,
+                   mu_wall: float = 2.0) -> List[LatticeSpec]:
+    """One replica per voxel of an n_x by n_z wall grid (voxel b*n_x + a at
+    temps[b*n_x + a]).  Vacancy counts follow a synthetic neutron flux of
+    the Eq. 11 shape, phi = exp(-mu_wall x) f(z) with a cosine axial profile
+    peaking mid-belt: nv = max(1, round(max_vac phi / phi_max)) (Eq. 12
+    ties the initial vacancy concentration to the local conditions without
+    a formula).  Compositions are drawn around the RPV solute fractions;
+    one alloy energy model for all; replica r uses Philox stream r."""
+    rng = np.random.default_rng(seed)
+    eps1, eps2, e0 = _rpv_alloy_model(rng)
+    reps = []
+    for b in range(n_z):
+        for a in range(n_x):
+            xv = (a + 0.5) / n_x
+            zv = (b + 0.5) / n_z
+            phi = np.exp(-mu_wall * xv) * np.sin(np.pi * zv)
+            nv = max(1, int(round(max_vac * phi)))
+            fr = {CU: rng.uniform(0.005, 0.020), NI: rng.uniform(0.0, 0.015),
+                  MN: rng.uniform(0.0, 0.015)}
+            occ = occupancy(rng, (cells, cells, cells), 5, fr, nv)
+            reps.append(LatticeSpec(dims=(cells, cells, cells), n_species=5, eps1=eps1,
+                                    eps2=eps2, e0=e0, nu=6.0e12,
+                                    temperature=float(temps[b * n_x + a]), occ=occ,
+                                    seed=seed, stream_id=len(reps)))
+    return reps
+
+
 def random_lattice(rng: np.random.Generator, dims, n_species: int,
                    n_vac: int, solute_total: float = 0.3,
                    temperature: float = 563.0) -> LatticeSpec:

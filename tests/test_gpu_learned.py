@@ -1,0 +1,214 @@
+"""GPU parity of the learned runtime forms (Sec. III-A): the local patch
+network on the 64-neighbour observation (akmc_patchnet_eval), the event
+loop with a policy choosing the events (Eq. 1-2, akmc_policy_attach) and
+with Poisson-time alignment (Eq. 5-7, akmc_poisson_attach), against the
+oracle (orc_patchnet_forward, orc_run_learned, orc_follow_learned).
+
+The network forward is the same binary32 sequence of operations on both
+sides, so its outputs are compared bit for bit.  Event sequences: binary64
+selection weights exp(z/tau) or rates summed in different orders (GPU tree,
+oracle left to right), so a trajectory may part only at a near tie; the
+oracle's follow mode replays the whole GPU log and checks every event: the
+chosen candidate's interval contains u1 * W up to 1e-12 of W, Gamma_tot
+within 1e-12, and dt within 1e-12 of the scale of Eq. 7's two terms (u(s)
+is summed in different orders too).  binary32 rates: the same checks at
+1e-5 against the oracle's binary32 mode.
+"""
+import numpy as np
+import pytest
+
+from paper_2604_24091_amd import akmc
+from paper_2604_24091_amd import workloads as W
+from tests.gpu_util import banner
+
+pytestmark = pytest.mark.gpu
+
+
+def _blob(rng, S, H, n_out, scale=0.5, bias3=0.0):
+    """Random network in a device blob and the oracle's copy of its stored
+    (bfloat16-rounded) parameters."""
+    from oracle import akmc_oracle as O
+    nb = akmc.PatchNetBlob(S, H, n_out)
+    nb.set(rng.normal(0, scale, (64, S, H)), rng.normal(0, 0.1, H),
+           rng.normal(0, scale / 4, (H, H)), rng.normal(0, 0.1, H),
+           rng.normal(0, scale / 4, (H, n_out)), np.full(n_out, bias3))
+    return nb, O.PatchNet(*nb.get())
+
+
+@pytest.mark.parametrize("S,H,n_out", [(3, 16, 8), (4, 64, 1), (5, 64, 8), (5, 33, 1), (8, 7, 8)])
+def test_patchnet_eval_bit_exact(oracle_mod, S, H, n_out):
+    import torch
+    banner("patchnet eval S=%d H=%d n_out=%d" % (S, H, n_out))
+    rng = np.random.default_rng(100 + S * H + n_out)
+    spec = W.random_lattice(rng, (5, 6, 7), S, 11, solute_total=0.4)
+    nb, net = _blob(rng, S, H, n_out)
+    sites = np.concatenate([rng.integers(0, spec.n_sites, 300), [-1, spec.n_sites, 0,
+                                                                  spec.n_sites - 1]]).astype(np.int32)
+    lat = akmc.Lattice(spec)
+    try:
+        d_sites = torch.as_tensor(sites, device="cuda")
+        out = torch.empty((sites.size, n_out), dtype=torch.float32, device="cuda")
+        akmc.patchnet_eval(lat.h, nb.blob, d_sites, sites.size, out)
+        torch.cuda.synchronize()
+        out = out.cpu().numpy()
+    finally:
+        lat.close()
+    o = oracle_mod.Oracle(spec)
+    for a, i in enumerate(sites):
+        if i < 0 or i >= spec.n_sites:
+            assert np.all(np.isnan(out[a]))
+            continue
+        ref = oracle_mod.patchnet_forward(net, o.observation(int(i)))
+        assert np.array_equal(out[a].view(np.uint32), ref.view(np.uint32)), (a, out[a], ref)
+
+
+def _run(spec, n, pol=None, tau=1.0, pt=None, chunks=None, **kw):
+    import torch
+    lat = akmc.Lattice(spec, **kw)
+    if pol is not None:
+        akmc.policy_attach(lat.h, pol.blob, tau)
+    if pt is not None:
+        akmc.poisson_attach(lat.h, pt.blob)
+    logs = []
+    for c in (chunks or [n]):
+        buf = lat.step(c, log=True)
+        torch.cuda.synchronize()
+        logs.append(akmc.log_to_numpy(buf, c))
+    occ, slots, s = lat.read()
+    lat.close()
+    return occ, slots, s, np.concatenate(logs)
+
+
+def _check_follow(oracle_mod, spec, gpu, pol, tau, pt, precision=0, tol=1e-12):
+    occ, slots, s, log = gpu
+    f = oracle_mod.Oracle(spec, precision=precision)
+    res = f.follow_learned(log, pol=pol, inv_tau=float(np.float32(1.0) / np.float32(tau)), pn=pt)
+    print("[gpu-case] follow: %s" % res, flush=True)
+    assert res["mismatches"] == 0
+    assert res["max_select_violation"] <= tol
+    assert res["max_gamma_rel"] <= tol
+    assert res["max_dt_rel"] <= tol
+    assert res["n_differ"] <= 1 + len(log) // 20000
+    assert np.array_equal(occ, f.occ) and np.array_equal(slots, f.slots)
+    assert s.digest == f.state.digest and s.n_events == f.state.n
+    if pt is None:
+        assert abs(s.t - f.state.t) <= 10 * tol * abs(f.state.t)
+    else:
+        # every dt was checked above; t is their running sum in event order
+        t = 0.0
+        for d in log["dt"]:
+            t += float(d)
+        assert s.t == t
+    return f
+
+
+@pytest.mark.parametrize("refresh", [akmc.REFRESH_LOCAL, akmc.REFRESH_FULL])
+def test_policy_loop_matches_oracle(oracle_mod, refresh):
+    """binary64 pair rates for time, events chosen by the policy."""
+    banner("policy loop refresh=%d" % refresh)
+    rng = np.random.default_rng(7)
+    spec = W.random_lattice(rng, (6, 6, 6), 4, 6, solute_total=0.2)
+    pol, pol_o = _blob(rng, 4, 32, 8, scale=0.6)
+    n = 3000
+    gpu = _run(spec, n, pol=pol, tau=0.8, refresh=refresh)
+    _check_follow(oracle_mod, spec, gpu, pol_o, 0.8, None)
+    o = oracle_mod.Oracle(spec)
+    done, log_o = o.run_learned(n, pol=pol_o, inv_tau=float(np.float32(1.0) / np.float32(0.8)), log=True)
+    same = np.array_equal(gpu[3]["to_site"], log_o["to_site"])
+    print("[gpu-case] policy trajectory identical to the oracle's run: %s" % same, flush=True)
+    if same:
+        assert gpu[2].digest == o.state.digest and np.array_equal(gpu[0], o.occ)
+
+
+def test_poisson_time_loop_matches_oracle(oracle_mod):
+    """Events chosen by the rates, time by Eq. 7."""
+    banner("poisson time loop")
+    rng = np.random.default_rng(8)
+    spec = W.random_lattice(rng, (6, 7, 5), 5, 8, solute_total=0.2)
+    pt, pt_o = _blob(rng, 5, 64, 1, scale=0.3, bias3=1.0)
+    gpu = _run(spec, 3000, pt=pt)
+    _check_follow(oracle_mod, spec, gpu, None, 1.0, pt_o)
+    dt = gpu[3]["dt"]
+    assert np.any(dt != dt[0])
+
+
+@pytest.mark.parametrize("refresh", [akmc.REFRESH_LOCAL, akmc.REFRESH_FULL])
+def test_policy_and_poisson_loop(oracle_mod, refresh):
+    """Both forms at once (AtomWorld's runtime): policy events, Poisson time;
+    and the same run in chunks gives the same state bit for bit."""
+    banner("policy + poisson loop refresh=%d" % refresh)
+    rng = np.random.default_rng(9)
+    spec = W.random_lattice(rng, (7, 6, 6), 5, 12, solute_total=0.25)
+    pol, pol_o = _blob(rng, 5, 64, 8, scale=0.5)
+    pt, pt_o = _blob(rng, 5, 48, 1, scale=0.3, bias3=2.0)
+    gpu = _run(spec, 4000, pol=pol, tau=1.3, pt=pt, refresh=refresh)
+    _check_follow(oracle_mod, spec, gpu, pol_o, 1.3, pt_o)
+    chunked = _run(spec, 4000, pol=pol, tau=1.3, pt=pt, refresh=refresh, chunks=[1, 999, 1500, 1500])
+    assert np.array_equal(chunked[0], gpu[0]) and chunked[2].digest == gpu[2].digest
+    assert chunked[2].t == gpu[2].t
+
+
+def test_local_refresh_equals_full_with_networks():
+    banner("learned local == full")
+    rng = np.random.default_rng(10)
+    spec = W.random_lattice(rng, (6, 6, 6), 4, 20, solute_total=0.2)
+    pol, _ = _blob(rng, 4, 64, 8)
+    pt, _ = _blob(rng, 4, 16, 1, bias3=1.0)
+    a = _run(spec, 2000, pol=pol, tau=0.9, pt=pt, refresh=akmc.REFRESH_LOCAL)
+    b = _run(spec, 2000, pol=pol, tau=0.9, pt=pt, refresh=akmc.REFRESH_FULL)
+    assert np.array_equal(a[0], b[0]) and a[2].digest == b[2].digest and a[2].t == b[2].t
+    assert np.array_equal(a[3]["dt"], b[3]["dt"])
+
+
+def test_learned_forms_binary32(oracle_mod):
+    """binary32 pair rates (the kernel's base-2 form against the oracle's
+    plain binary32 law): every event checked at 1e-5."""
+    banner("learned forms binary32")
+    rng = np.random.default_rng(11)
+    spec = W.random_lattice(rng, (6, 6, 6), 5, 7, solute_total=0.2)
+    pol, pol_o = _blob(rng, 5, 32, 8, scale=0.5)
+    pt, pt_o = _blob(rng, 5, 32, 1, scale=0.3, bias3=1.0)
+    gpu = _run(spec, 2000, pol=pol, tau=1.0, pt=pt, precision=akmc.FP32)
+    _check_follow(oracle_mod, spec, gpu, pol_o, 1.0, pt_o, precision=1, tol=1e-5)
+
+
+def test_learned_forms_on_the_4m_lattice(oracle_mod):
+    """The 128^3-cell workload (200 vacancies, binary32 rates) with a policy
+    of hidden width 64 and a Poisson network: 3,000 events, each followed by
+    the oracle."""
+    banner("learned forms rpv_4m 3000 events")
+    rng = np.random.default_rng(12)
+    spec = W.rpv_4m()
+    pol, pol_o = _blob(rng, 5, 64, 8, scale=0.5)
+    pt, pt_o = _blob(rng, 5, 64, 1, scale=0.3, bias3=1.0)
+    gpu = _run(spec, 3000, pol=pol, tau=1.0, pt=pt, precision=akmc.FP32)
+    _check_follow(oracle_mod, spec, gpu, pol_o, 1.0, pt_o, precision=1, tol=1e-5)
+
+
+def test_attach_errors():
+    banner("learned attach errors")
+    rng = np.random.default_rng(13)
+    small = W.random_lattice(rng, (4, 5, 5), 4, 2)
+    lat = akmc.Lattice(small)
+    pol, _ = _blob(rng, 4, 8, 8)
+    pt, _ = _blob(rng, 4, 8, 1)
+    try:
+        with pytest.raises(akmc.AkmcError):          # edges below 5 cells
+            akmc.policy_attach(lat.h, pol.blob, 1.0)
+    finally:
+        lat.close()
+    spec = W.random_lattice(rng, (5, 5, 5), 4, 2)
+    lat = akmc.Lattice(spec)
+    try:
+        with pytest.raises(akmc.AkmcError):          # a Poisson blob as policy
+            akmc.policy_attach(lat.h, pt.blob, 1.0)
+        with pytest.raises(akmc.AkmcError):          # tau
+            akmc.policy_attach(lat.h, pol.blob, 0.0)
+        other, _ = _blob(rng, 3, 8, 1)
+        with pytest.raises(akmc.AkmcError):          # species count
+            akmc.poisson_attach(lat.h, other.blob)
+        akmc.policy_attach(lat.h, pol.blob, 1.0)
+        akmc.policy_attach(lat.h, None, 1.0)         # detach
+        lat.step(10)
+    finally:
+        lat.close()

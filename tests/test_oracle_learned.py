@@ -247,3 +247,28 @@ def test_poisson_time_with_the_exact_first_passage_time(oracle_mod):
             assert abs(d - (tau[idx[s]] - (tau[idx[t]] if t in idx else 0.0))) <= 1e-9 * tau.max()
             mean += rates[s][k] / g * d
         assert abs(mean * g - 1.0) <= 1e-9
+
+
+def test_follow_learned_accepts_its_own_log_and_flags_a_wrong_one(oracle_mod):
+    """The learned follow mode replays a run's own log with no violation
+    and exact times, and flags a log whose choice was altered."""
+    rng = np.random.default_rng(13)
+    spec = W.random_lattice(rng, (5, 5, 5), 4, 3, solute_total=0.2)
+    pol = _net(rng, spec.n_species, 16, 8, scale=0.6)
+    pn = _net(rng, spec.n_species, 16, 1, scale=0.3, bias3=1.5)
+    a = oracle_mod.Oracle(spec)
+    done, log = a.run_learned(300, pol=pol, inv_tau=1.25, pn=pn, log=True)
+    assert done == 300
+    f = oracle_mod.Oracle(spec)
+    res = f.follow_learned(log, pol=pol, inv_tau=1.25, pn=pn)
+    assert res["mismatches"] == 0 and res["n_differ"] == 0
+    assert res["max_select_violation"] == 0.0 and res["max_dt_rel"] == 0.0
+    assert res["max_gamma_rel"] == 0.0
+    assert f.state.digest == a.state.digest and f.state.t == a.state.t
+    bad = log.copy()
+    e = 120
+    alt = [k for k in range(8) if k != int(bad["dir"][e])]
+    bad["dir"][e] = alt[0]
+    g = oracle_mod.Oracle(spec)
+    res = g.follow_learned(bad, pol=pol, inv_tau=1.25, pn=pn)
+    assert res["mismatches"] == 1 or res["n_differ"] >= 1
