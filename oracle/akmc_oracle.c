@@ -75,6 +75,9 @@ typedef struct {
     uint64_t stream_id;
     int32_t precision;           /* 0 = binary64, 1 = binary32 energies/rates */
     int32_t time_mode;           /* 0 = -ln(u2)/G, 1 = 1/G */
+    int32_t n_shells;            /* 2 (1NN, 2NN) or 6 (every pair within 6.0 A) */
+    int32_t pad_;
+    double epsx[4][64];          /* shells 3..6 when n_shells = 6, S*S row-major, eV */
 } orc_params;
 
 typedef struct {
@@ -174,9 +177,30 @@ static int counts(const orc_params *p, const uint8_t *occ, int32_t i, int k,
     return occ[j];
 }
 
+/* The pair model out to 6.0 A (n_shells = 6): the bonds of shells 1-6 (the
+ * 64 neighbours of the observation, 8, 6, 12, 24, 8, 6 per shell).  The
+ * jump changes the bonds of i and j in every shell, so
+ *   dn[m][s] = #{n in N_m(i)\{j}: s} - #{n in N_m(j)\{i}: s}
+ * (j lies only in the first shell of i, and i in the first shell of j).
+ * Defined after the observation offsets below. */
+static int counts6(const orc_params *p, const uint8_t *occ, int32_t i, int k, int dn[6][8]);
+
+static const double *shell_eps(const orc_params *p, int m) {
+    return m == 0 ? p->eps1 : m == 1 ? p->eps2 : p->epsx[m - 2];
+}
+
 /* Energy change of the jump, binary64.  Returns NaN for a masked jump. */
 double orc_delta_e(const orc_params *p, const uint8_t *occ, int32_t i, int k) {
     int S = p->n_species, dn1[8], dn2[8];
+    if (p->n_shells == 6) {
+        int dn[6][8];
+        int A = counts6(p, occ, i, k, dn);
+        if (A == S - 1) return NAN;
+        double acc = 0.0;
+        for (int m = 0; m < 6; m++)
+            for (int s = 0; s < S; s++) acc = fma((double)dn[m][s], dtab(shell_eps(p, m), S, A, s), acc);
+        return acc;
+    }
     int A = counts(p, occ, i, k, dn1, dn2);
     if (A == S - 1) return NAN;
     double acc = 0.0;
@@ -190,12 +214,36 @@ double orc_delta_e(const orc_params *p, const uint8_t *occ, int32_t i, int k) {
  * rate = +0. */
 static void candidate(const orc_params *p, const uint8_t *occ, int32_t i, int k,
                       double *ea_out, double *de_out, double *rate_out) {
-    int S = p->n_species, dn1[8], dn2[8];
-    int A = counts(p, occ, i, k, dn1, dn2);
+    int S = p->n_species, dn1[8], dn2[8], dn[6][8];
+    int A = p->n_shells == 6 ? counts6(p, occ, i, k, dn) : counts(p, occ, i, k, dn1, dn2);
     if (A == S - 1) {
         *ea_out = INFINITY;
         *de_out = NAN;
         *rate_out = 0.0;
+        return;
+    }
+    if (p->n_shells == 6) {
+        /* shells 1-6 in order, species in order: one fma chain */
+        double acc = 0.0;
+        float accf = 0.0f;
+        for (int m = 0; m < 6; m++)
+            for (int s = 0; s < S; s++) {
+                acc = fma((double)dn[m][s], dtab(shell_eps(p, m), S, A, s), acc);
+                accf = fmaf((float)dn[m][s], (float)dtab(shell_eps(p, m), S, A, s), accf);
+            }
+        if (p->precision == 0) {
+            double ea = p->e0[A] + 0.5 * acc;
+            double kt = p->kb * p->temperature;
+            *ea_out = ea;
+            *de_out = acc;
+            *rate_out = p->nu * exp(-(ea / kt));
+        } else {
+            float ea = (float)p->e0[A] + 0.5f * accf;
+            float kt = (float)(p->kb * p->temperature);
+            *ea_out = (double)ea;
+            *de_out = (double)accf;
+            *rate_out = (double)((float)p->nu * expf(-(ea / kt)));
+        }
         return;
     }
     if (p->precision == 0) {
@@ -423,7 +471,10 @@ static int64_t run_events(const orc_params *p, uint8_t *occ, int32_t *slots, int
         done += 1;
         if (local)
             for (int32_t u = 0; u < nv; u++) {
-                if (half_dist(p, slots[u], i) > 3 && half_dist(p, slots[u], j) > 3) continue;
+                /* a candidate's bonds lie within 3 half-cells of its vacancy
+                 * (5 for the pair model out to 6.0 A) */
+                int reach = p->n_shells == 6 ? 5 : 3;
+                if (half_dist(p, slots[u], i) > reach && half_dist(p, slots[u], j) > reach) continue;
                 for (int kk = 0; kk < 8; kk++) {
                     double ea, r;
                     orc_candidate(p, occ, slots[u], kk, &ea, &r);
@@ -901,4 +952,26 @@ void orc_follow_learned(const orc_params *p, uint8_t *occ, int32_t *slots, int32
     }
     free(rates);
     free(w);
+}
+
+/* ------------------------------------------------ pair model out to 6.0 A */
+
+static int shell_of_offset(const int d[3]) {
+    int r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    return r2 == 3 ? 0 : r2 == 4 ? 1 : r2 == 8 ? 2 : r2 == 11 ? 3 : r2 == 12 ? 4 : r2 == 16 ? 5 : -1;
+}
+
+static int counts6(const orc_params *p, const uint8_t *occ, int32_t i, int k, int dn[6][8]) {
+    int32_t j = orc_nbr1(p, i, k);
+    obs_build();
+    for (int m = 0; m < 6; m++)
+        for (int s = 0; s < 8; s++) dn[m][s] = 0;
+    for (int q = 0; q < 64; q++) {
+        int sh = shell_of_offset(obs_off[q]);
+        int32_t a = offset_site(p, i, obs_off[q][0], obs_off[q][1], obs_off[q][2]);
+        int32_t b = offset_site(p, j, obs_off[q][0], obs_off[q][1], obs_off[q][2]);
+        if (a != j) dn[sh][occ[a]] += 1;
+        if (b != i) dn[sh][occ[b]] -= 1;
+    }
+    return occ[j];
 }

@@ -23,7 +23,8 @@ class OrcParams(C.Structure):
                 ("e0", C.c_double * 8),
                 ("nu", C.c_double), ("temperature", C.c_double), ("kb", C.c_double),
                 ("seed", C.c_uint64), ("stream_id", C.c_uint64),
-                ("precision", C.c_int32), ("time_mode", C.c_int32)]
+                ("precision", C.c_int32), ("time_mode", C.c_int32),
+                ("n_shells", C.c_int32), ("pad_", C.c_int32), ("epsx", (C.c_double * 64) * 4)]
 
 
 class OrcEvent(C.Structure):
@@ -175,6 +176,15 @@ def make_params(spec, precision: int = 0, time_mode: int = 0,
     p.stream_id = int(spec.stream_id) & (2**64 - 1)
     p.precision = int(precision)
     p.time_mode = int(time_mode)
+    # the pair model out to 6.0 A: shells 3..6 from spec.eps_far [4][S][S]
+    far = getattr(spec, "eps_far", None)
+    p.n_shells = 2 if far is None else 6
+    if far is not None:
+        far = np.asarray(far, dtype=np.float64).reshape(4, S, S)
+        for m in range(4):
+            for a in range(S):
+                for b in range(S):
+                    p.epsx[m][a * S + b] = far[m, a, b]
     return p
 
 

@@ -41,6 +41,9 @@ class LatticeSpec:
     seed: int = 0               # Philox key word 0
     stream_id: int = 0          # Philox key word 1
     kb: float = KB_EV_PER_K
+    # Pair model out to 6.0 A: (4, S, S) symmetric energies of shells 3..6
+    # (None: first and second neighbours only)
+    eps_far: Optional[np.ndarray] = None
 
     @property
     def n_sites(self) -> int:
@@ -126,6 +129,31 @@ def rpv_alloy(cells: int, n_vac: int, seed: int) -> LatticeSpec:
     return LatticeSpec(dims=(cells, cells, cells), n_species=5, eps1=eps1,
                        eps2=eps2, e0=e0, nu=6.0e12, temperature=563.0, occ=occ,
                        seed=seed, stream_id=0)
+
+
+def far_tables(rng: np.random.Generator, n_species: int, scale=(0.10, 0.06, 0.04, 0.03)) -> np.ndarray:
+    """Symmetric pair energies of shells 3..6 (eV), i.i.d. U[-c, c] per
+    unordered pair with c shrinking with distance: a stand-in for a
+    longer-ranged landscape (vacancy rows included)."""
+    out = np.zeros((4, n_species, n_species))
+    for m, c in enumerate(scale):
+        for a in range(n_species):
+            for b in range(a, n_species):
+                out[m, a, b] = out[m, b, a] = rng.uniform(-c, c)
+    return out
+
+
+def rpv_alloy_far(cells: int, n_vac: int, seed: int) -> LatticeSpec:
+    """The Fe-1.34Cu-0.70Ni-1.40Mn solid solution with the pair model out to
+    6.0 A (shells 1-6, the 64-neighbour range of Sec. IV-C)."""
+    spec = rpv_alloy(cells, n_vac, seed)
+    spec.eps_far = far_tables(np.random.default_rng(seed + 7919), 5)
+    return spec
+
+
+def rpv_4m_far(seed: int = 1005) -> LatticeSpec:
+    """128^3 cells, 200 vacancies, pairs out to 6.0 A."""
+    return rpv_alloy_far(128, 200, seed)
 
 
 def rpv_524k(seed: int = 1001) -> LatticeSpec:

@@ -2,7 +2,8 @@
 
 Neighbours are found from Cartesian positions (units of a/2) by minimum-image
 squared distance: 3 for first neighbours (half body diagonal), 4 for second
-neighbours (one cube edge).  Nothing here calls the oracle; the tests use it
+neighbours (one cube edge), and 8, 11, 12, 16 for shells 3-6 (the pairs
+within 6.0 A).  Nothing here calls the oracle; the tests use it
 to pin the oracle's neighbour tables and its local energy change.
 """
 import numpy as np
@@ -40,3 +41,25 @@ def total_energy(occ, eps1, eps2, adj1, adj2):
     e1 = eps1[occ[:, None], occ[None, :]]
     e2 = eps2[occ[:, None], occ[None, :]]
     return 0.5 * (e1[adj1].sum() + e2[adj2].sum())
+
+
+SHELL_D2 = (3, 4, 8, 11, 12, 16)
+
+
+def shells6(dims):
+    """Adjacency matrices of shells 1-6 by minimum-image squared distance."""
+    pos = positions(dims)
+    box = 2 * np.array(dims, dtype=np.int64)
+    disp = min_image(pos[None, :, :] - pos[:, None, :], box[None, None, :])
+    d2 = (disp ** 2).sum(-1)
+    return [d2 == r for r in SHELL_D2]
+
+
+def total_energy6(occ, eps, adj):
+    """E = 1/2 sum_shells sum_p sum_{q in N_m(p)} eps[m][s_p, s_q]."""
+    occ = np.asarray(occ, dtype=np.int64)
+    e = 0.0
+    for m in range(6):
+        em = eps[m][occ[:, None], occ[None, :]]
+        e += 0.5 * em[adj[m]].sum()
+    return e
