@@ -102,6 +102,18 @@ typedef struct akmc_params {
     int32_t refresh;           /* AKMC_REFRESH_LOCAL or AKMC_REFRESH_FULL */
     int32_t time_mode;         /* AKMC_TIME_STOCHASTIC or AKMC_TIME_MEAN */
     int32_t barrier_model;     /* AKMC_BARRIER_PAIR or AKMC_BARRIER_MLP */
+    /* Range of the pair model: 2 (first and second neighbours, eps1, eps2)
+     * or 6 (every pair within 6.0 A: shells 1-6 with 8, 6, 12, 24, 8, 6
+     * neighbours, the 64-neighbour range of Sec. IV-C; shells 3-6 in
+     * eps_far[0..3], same layout as eps1).  With 6 shells the energy change
+     * is the integer species counts of the changed bonds of every shell
+     * times D_m[A][s] = eps_m[A][s] - eps_m[S-1][s], one fused multiply-add
+     * chain over shells 1..6 then species; edges must be >= 5 cells; the
+     * learned barrier, the learned runtime forms and batches are not
+     * available for it (UNSUPPORTED). */
+    int32_t n_shells;
+    int32_t pad_;
+    double eps_far[4][64];
 } akmc_params;
 
 /* One executed event (40 bytes). */

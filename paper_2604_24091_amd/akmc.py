@@ -38,7 +38,8 @@ class Params(C.Structure):
                 ("seed", C.c_uint64), ("stream_id", C.c_uint64),
                 ("event_counter0", C.c_int64), ("time0", C.c_double), ("digest0", C.c_uint64),
                 ("precision", C.c_int32), ("refresh", C.c_int32), ("time_mode", C.c_int32),
-                ("barrier_model", C.c_int32)]
+                ("barrier_model", C.c_int32), ("n_shells", C.c_int32), ("pad_", C.c_int32),
+                ("eps_far", (C.c_double * 64) * 4)]
 
 
 class Event(C.Structure):
@@ -217,6 +218,14 @@ def make_params(spec, precision: int = FP64, refresh: int = REFRESH_LOCAL,
     p.refresh = int(refresh)
     p.time_mode = int(time_mode)
     p.barrier_model = int(barrier_model)
+    far = getattr(spec, "eps_far", None)
+    p.n_shells = 2 if far is None else 6
+    if far is not None:
+        far = np.asarray(far, dtype=np.float64).reshape(4, S, S)
+        for m in range(4):
+            for a in range(S):
+                for b in range(S):
+                    p.eps_far[m][a * S + b] = far[m, a, b]
     return p
 
 

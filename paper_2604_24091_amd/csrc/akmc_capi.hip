@@ -75,6 +75,18 @@ akmc_status check_params(const akmc_params *p) {
   if (p->barrier_model != AKMC_BARRIER_PAIR && p->barrier_model != AKMC_BARRIER_MLP)
     return fail(AKMC_ERR_INVALID, "barrier_model must be PAIR or MLP");
   if (p->event_counter0 < 0) return fail(AKMC_ERR_INVALID, "event_counter0 must be >= 0");
+  if (p->n_shells != 2 && p->n_shells != 6) return fail(AKMC_ERR_INVALID, "n_shells must be 2 or 6");
+  if (p->n_shells == 6) {
+    if (p->lx < 5 || p->ly < 5 || p->lz < 5)
+      return fail(AKMC_ERR_INVALID, "the pair model out to 6.0 A needs lattice edges of at least 5 cells");
+    for (int m = 0; m < 4; ++m)
+      for (int a = 0; a < S; ++a)
+        for (int b = 0; b < S; ++b) {
+          const double e = p->eps_far[m][a * S + b];
+          if (!std::isfinite(e)) return fail(AKMC_ERR_INVALID, "pair energies must be finite");
+          if (e != p->eps_far[m][b * S + a]) return fail(AKMC_ERR_INVALID, "pair energy tables must be symmetric");
+        }
+  }
   if (!std::isfinite(p->time0)) return fail(AKMC_ERR_INVALID, "time0 must be finite");
   return AKMC_OK;
 }
@@ -153,6 +165,15 @@ LatDesc make_desc(const akmc_params *p, int nv) {
     field = std::max(field, 8.0 * m1 + 6.0 * m2);
   }
   d.sweep_factor_ok = cmax + field <= 700.0 ? 1 : 0;
+  d.n_shells = p->n_shells;
+  if (p->n_shells == 6)
+    for (int m = 0; m < 4; ++m)
+      for (int A = 0; A < S; ++A)
+        for (int s = 0; s < S; ++s) {
+          const double dx = p->eps_far[m][A * S + s] - p->eps_far[m][V * S + s];
+          d.Dx[m][A * 8 + s] = dx;
+          d.Dxf[m][A * 8 + s] = (float)dx;
+        }
   return d;
 }
 
@@ -247,6 +268,8 @@ akmc_status akmc_lattice_create(const akmc_params *p, const uint8_t *occ_host,
   if (!aligned(d_ws)) return fail(AKMC_ERR_INVALID, "workspace must be 256-byte aligned");
   if (p->barrier_model == AKMC_BARRIER_MLP && p->precision != AKMC_FP32)
     return fail(AKMC_ERR_UNSUPPORTED, "the learned barrier gives binary32 rates: use precision AKMC_FP32");
+  if (p->barrier_model == AKMC_BARRIER_MLP && p->n_shells == 6)
+    return fail(AKMC_ERR_UNSUPPORTED, "the learned barrier reads the two-shell bond footprint: use n_shells 2");
   const int64_t N = n_sites_of(p);
   std::vector<int32_t> slots;
   st = build_slots(p, occ_host, slot_sites_host, slots);
@@ -373,6 +396,9 @@ static akmc_status run_loop(akmc_handle h, int64_t n_events, double t_end, akmc_
   a.t_end = t_end;
   const bool lrn = h->pol_blob || h->pt_blob;
   if (lrn && mlp) return fail(AKMC_ERR_UNSUPPORTED, "the learned runtime forms use the pair barrier model");
+  const bool far = h->p.n_shells == 6;
+  if (far && event_loop_far_lds_bytes(h->nv, h->p.precision) > kLdsBytes)
+    return fail(AKMC_ERR_UNSUPPORTED, "the vacancies' rate tree needs more than the 160 KiB of LDS of a workgroup");
   a.pol_blob = h->pol_blob;
   a.pt_blob = h->pt_blob;
   a.inv_tau = h->inv_tau;
@@ -391,7 +417,8 @@ static akmc_status run_loop(akmc_handle h, int64_t n_events, double t_end, akmc_
     a.log = d_log ? d_log + done : nullptr;
     a.log_stride = n;
     const int full = h->p.refresh == AKMC_REFRESH_FULL;
-    hipError_t e = lrn  ? launch_event_loop_lrn(a, h->p.precision, full, lrn_lds, h->stream)
+    hipError_t e = far  ? launch_event_loop_far(a, h->p.precision, full, h->stream)
+                   : lrn  ? launch_event_loop_lrn(a, h->p.precision, full, lrn_lds, h->stream)
                    : mlp ? launch_event_loop_mlp(a, full, h->p.n_species, h->stream)
                          : launch_event_loop(a, h->p.precision, full, s, h->stream);
     if (e != hipSuccess) return hip_fail(e, "kmc_step launch");
@@ -728,6 +755,8 @@ akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p, const uint8_t
       return fail(AKMC_ERR_INVALID, "precision and refresh must agree across replicas");
     if (p[r].barrier_model != AKMC_BARRIER_PAIR)
       return fail(AKMC_ERR_UNSUPPORTED, "batches use the pair barrier model");
+    if (p[r].n_shells != 2)
+      return fail(AKMC_ERR_UNSUPPORTED, "batches use the first-and-second-neighbour pair model");
     s = build_slots(&p[r], occ_host[r], slot_sites_host ? slot_sites_host[r] : nullptr, slots[r]);
     if (s != AKMC_OK) return s;
     nv[r] = (int32_t)slots[r].size();
@@ -1043,6 +1072,8 @@ akmc_status akmc_mlp_get_params(const void *d_blob, int32_t n_species, float *ho
 akmc_status akmc_env_encode(akmc_handle h, int32_t mode, const int32_t *d_sites, int64_t n_sites,
                             uint8_t *d_env, float *d_ea) {
   if (!h || !d_env) return fail(AKMC_ERR_INVALID, "handle or output is NULL");
+  if (h->p.n_shells != 2)
+    return fail(AKMC_ERR_UNSUPPORTED, "the surrogate's environment covers the first two shells only");
   const int32_t *sites;
   int64_t n;
   switch (mode) {
@@ -1285,8 +1316,8 @@ static akmc_status attach_net(akmc_handle h, const void *d_blob, int want_out, c
   if (hdr.S != h->p.n_species) return fail(AKMC_ERR_INVALID, "network species count differs from the lattice's");
   if (h->p.lx < 5 || h->p.ly < 5 || h->p.lz < 5)
     return fail(AKMC_ERR_INVALID, "the 64-neighbour observation needs lattice edges of at least 5 cells");
-  if (h->p.barrier_model != AKMC_BARRIER_PAIR)
-    return fail(AKMC_ERR_UNSUPPORTED, "the learned runtime forms use the pair barrier model");
+  if (h->p.barrier_model != AKMC_BARRIER_PAIR || h->p.n_shells != 2)
+    return fail(AKMC_ERR_UNSUPPORTED, "the learned runtime forms use the first-and-second-neighbour pair model");
   const int d[3] = {hdr.S, hdr.H, hdr.n_out};
   const unsigned char *pol = want_out == 8 ? static_cast<const unsigned char *>(d_blob) : h->pol_blob;
   const unsigned char *pt = want_out == 1 ? static_cast<const unsigned char *>(d_blob) : h->pt_blob;

@@ -147,6 +147,29 @@ __device__ __forceinline__ Real delta_e_counts(uint32_t c1i, uint32_t c1j, uint3
   return acc;
 }
 
+// Pair model out to 6.0 A: the energy change from per-shell species counts
+// of the changed bonds, ci[m] (of i without j) and cj[m] (of j without i)
+// holding one 8-bit count per species (shells hold at most 24 sites), as
+// one fused multiply-add chain over shells 1..6, then species: shell 1 and
+// 2 tables D1, D2, shells 3..6 in Dx (rows of 8 at 8*A, stride 64).
+template <class Real>
+__device__ __forceinline__ Real delta_e_counts6(const uint64_t (&ci)[6], const uint64_t (&cj)[6], int S,
+                                                const Real *D1row, const Real *D2row, const Real *Dx,
+                                                int A) {
+  Real acc = Real(0);
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const Real *row = m == 0 ? D1row : m == 1 ? D2row : Dx + 64 * (m - 2) + 8 * A;
+#pragma unroll
+    for (int sp = 0; sp < 8; ++sp) {
+      if (sp >= S) break;
+      const int dn = (int)((ci[m] >> (8 * sp)) & 255u) - (int)((cj[m] >> (8 * sp)) & 255u);
+      acc = fma(Real(dn), row[sp], acc);
+    }
+  }
+  return acc;
+}
+
 __device__ __forceinline__ double rate_from_barrier(double ea, double nu, double kT) {
   double x = -(ea / kT);
   return nu * exp(x);

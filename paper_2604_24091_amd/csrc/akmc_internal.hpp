@@ -48,6 +48,12 @@ struct LatDesc {
   // exp(700) either way for these tables (else the sweep is not used)
   int32_t sweep_factor_ok;
   int32_t pad2_;
+  // Pair model out to 6.0 A (n_shells = 6): rows A at 8*A of
+  // D_m[A][s] = eps_m[A][s] - eps_m[V][s] for shells m = 3..6.
+  int32_t n_shells;
+  int32_t pad3_;
+  double Dx[4][64];
+  float Dxf[4][64];
 };
 
 // Mutable per-lattice state.
@@ -97,6 +103,7 @@ struct LoopArgs {
 // children: level 1 over slot totals, level l+1 over the last partial of
 // each level-l group, until one group of at most 8 nodes remains.
 constexpr int kBoxBytes = 352;   // 7x7x7 footprint box, padded to 16
+constexpr int kBoxBytesFar = 1344;  // 11x11x11 box of the pair model out to 6.0 A
 constexpr int kMaxLevels = 3;
 static_assert(AKMC_MAX_VACANCIES <= 8 * 8 * 8, "three levels of groups of 8 cover every slot");
 
@@ -110,7 +117,8 @@ struct GroupLayout {
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-__host__ __device__ inline GroupLayout make_layout(int nv_max, int G, int fp32) {
+// far: the pair model out to 6.0 A (11x11x11 boxes, tables of 6 shells).
+__host__ __device__ inline GroupLayout make_layout(int nv_max, int G, int fp32, int far = 0) {
   GroupLayout L{};
   L.nv_max = nv_max;
   L.G = G;
@@ -134,8 +142,8 @@ __host__ __device__ inline GroupLayout make_layout(int nv_max, int G, int fp32) 
   L.off_la = o;   o = align16(o + nv_max * 4);
   L.off_lb = o;   o = align16(o + nv_max * 4);
   L.off_spec = o; o = align16(o + nv_max * 8);
-  L.off_box = o;  o = align16(o + (G / 8) * kBoxBytes);
-  L.off_tab = o;  o = align16(o + (64 + 64 + 8) * real);
+  L.off_box = o;  o = align16(o + (G / 8) * (far ? kBoxBytesFar : kBoxBytes));
+  L.off_tab = o;  o = align16(o + (64 + 64 + 8 + (far ? 4 * 64 : 0)) * real);
   L.off_rng = o;  o = align16(o + 2 * G * 8);
   L.off_tmp = o;  o = align16(o + G * 8);
   L.bytes = o;
@@ -157,6 +165,9 @@ hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_spec
 size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision);
 // Event loop with the learned runtime forms (one 64-lane group); lds from
 // event_loop_lrn_lds_bytes with each attached network's (S, H, n_out).
+// Event loop of the pair model out to 6.0 A (one 64-lane group).
+hipError_t launch_event_loop_far(const LoopArgs &a, int precision, int refresh_full, hipStream_t stream);
+size_t event_loop_far_lds_bytes(int nv_max, int precision);
 hipError_t launch_event_loop_lrn(const LoopArgs &a, int precision, int refresh_full, size_t lds,
                                  hipStream_t stream);
 size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3],

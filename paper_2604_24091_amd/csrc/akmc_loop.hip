@@ -81,15 +81,80 @@ constexpr int kFarOff = 344;
 static_assert(kFarOff >= 343 && kFarOff + 6 <= kBoxBytes, "far sites fit the box padding");
 constexpr int kFarD[6][3] = {{-4, 0, 0}, {0, -4, 0}, {0, 0, -4}, {0, 0, 4}, {0, 4, 0}, {4, 0, 0}};
 
-// Packed gather element: box byte (bits 0-8; the index 0..5 of a far site),
-// offsets + 4 (bits 9-12, 13-16, 17-20), box number q (bits 21-26), centre
-// flag (bit 27), far flag (bit 28); -1 for none.
-__device__ __forceinline__ int fe_dx(int f) { return ((f >> 9) & 15) - 4; }
-__device__ __forceinline__ int fe_dy(int f) { return ((f >> 13) & 15) - 4; }
-__device__ __forceinline__ int fe_dz(int f) { return ((f >> 17) & 15) - 4; }
-__device__ __forceinline__ int fe_q(int f) { return (f >> 21) & 63; }
-__device__ __forceinline__ bool fe_centre(int f) { return (f >> 27) & 1; }
-__device__ __forceinline__ int fe_byte(int f) { return ((f >> 28) & 1) ? kFarOff + (f & 511) : (f & 511); }
+// Packed gather element: box byte (bits 0-10; the index 0..5 of a far site),
+// offsets + 5 (bits 11-14, 15-18, 19-22), box number q (bits 23-28), centre
+// flag (bit 29), far flag (bit 30); -1 for none.
+__host__ __device__ constexpr int fe_pack(int bi, int dx, int dy, int dz, int q, bool centre, bool far) {
+  return bi | ((dx + 5) << 11) | ((dy + 5) << 15) | ((dz + 5) << 19) | (q << 23) | ((int)centre << 29) |
+         ((int)far << 30);
+}
+__device__ __forceinline__ int fe_dx(int f) { return ((f >> 11) & 15) - 5; }
+__device__ __forceinline__ int fe_dy(int f) { return ((f >> 15) & 15) - 5; }
+__device__ __forceinline__ int fe_dz(int f) { return ((f >> 19) & 15) - 5; }
+__device__ __forceinline__ int fe_q(int f) { return (f >> 23) & 63; }
+__device__ __forceinline__ bool fe_centre(int f) { return (f >> 29) & 1; }
+__device__ __forceinline__ int fe_byte(int f) { return ((f >> 30) & 1) ? kFarOff + (f & 2047) : (f & 2047); }
+
+// Pair model out to 6.0 A: an 11x11x11 box (offsets -5..5) holds the bonds
+// of all 8 jumps of a vacancy: the 168 sites within 6.0 A of the vacancy or
+// of one of its 8 targets.
+constexpr int kBoxCF = 5 + 11 * 5 + 121 * 5;
+constexpr int kFootFarN = 168;
+struct FootFarTab {
+  int8_t d[kFootFarN][3];
+  int n;
+};
+constexpr bool within_6a(int dx, int dy, int dz) {
+  const int odd = dx & 1;
+  if ((dy & 1) != odd || (dz & 1) != odd) return false;
+  const int r2 = dx * dx + dy * dy + dz * dz;
+  return r2 > 0 && r2 <= 16;
+}
+constexpr FootFarTab make_foot_far() {
+  FootFarTab t{};
+  int n = 0;
+  for (int dz = -5; dz <= 5; ++dz)
+    for (int dy = -5; dy <= 5; ++dy)
+      for (int dx = -5; dx <= 5; ++dx) {
+        if (dx == 0 && dy == 0 && dz == 0) continue;
+        bool in = within_6a(dx, dy, dz);
+        for (int k = 0; k < 8 && !in; ++k) {
+          const int tx = (k >> 2) & 1 ? 1 : -1, ty = (k >> 1) & 1 ? 1 : -1, tz = k & 1 ? 1 : -1;
+          in = (dx == tx && dy == ty && dz == tz) || within_6a(dx - tx, dy - ty, dz - tz);
+        }
+        if (!in) continue;
+        if (n < kFootFarN) {
+          t.d[n][0] = (int8_t)dx;
+          t.d[n][1] = (int8_t)dy;
+          t.d[n][2] = (int8_t)dz;
+        }
+        ++n;
+      }
+  t.n = n;
+  return t;
+}
+constexpr FootFarTab kFootFarHost = make_foot_far();
+static_assert(kFootFarHost.n == kFootFarN, "the bonds of a vacancy's 8 jumps touch 168 sites");
+__constant__ FootFarTab kFootFar = make_foot_far();
+
+// The 64 bond offsets with their shells (the observation order), as box
+// offsets of the 11x11x11 box.
+struct BondFar {
+  int16_t off[kObsN];
+  int8_t sh[kObsN];
+};
+constexpr BondFar make_bond_far() {
+  BondFar r{};
+  const ObsTab t = make_obs();
+  for (int m = 0; m < kObsN; ++m) {
+    const int dx = t.d[m][0], dy = t.d[m][1], dz = t.d[m][2];
+    const int r2 = dx * dx + dy * dy + dz * dz;
+    r.off[m] = (int16_t)(dx + 11 * dy + 121 * dz);
+    r.sh[m] = (int8_t)(r2 == 3 ? 0 : r2 == 4 ? 1 : r2 == 8 ? 2 : r2 == 11 ? 3 : r2 == 12 ? 4 : 5);
+  }
+  return r;
+}
+__constant__ BondFar kBondFar = make_bond_far();
 
 // Box byte of each observation neighbour: inside the 7x7x7 box, or the far
 // slot of an axis site 4 half-cells away.
@@ -146,6 +211,7 @@ struct Lds {
   uint8_t *spec;    // [nv][8] species of each candidate's target
   uint8_t *box;     // (G/8) footprint boxes
   Real *D1, *D2, *e0;
+  Real *Dx;         // shells 3..6 of the pair model out to 6.0 A (4 rows of 64)
   double *ru1, *rw; // uniforms u1 and -ln u2 of the next G events
   double *tmp;      // G values exchanged between the lanes of a group
 };
@@ -164,6 +230,7 @@ __device__ __forceinline__ Lds<Real> carve(unsigned char *base, const GroupLayou
   s.D1 = (Real *)(base + L.off_tab);
   s.D2 = s.D1 + 64;
   s.e0 = s.D2 + 64;
+  s.Dx = s.e0 + 8;
   s.ru1 = (double *)(base + L.off_rng);
   s.rw = s.ru1 + L.G;
   s.tmp = (double *)(base + L.off_tmp);
@@ -203,6 +270,37 @@ __device__ __forceinline__ double eval_box(const uint8_t *box, int k, int V, con
   return (double)rate_from_barrier(ea, nu, kT);
 }
 
+// Rate of candidate k with the pair model out to 6.0 A (box of 11^3, 4 *
+// species per byte): per-shell species counts of the 63 bonds of i without
+// j and of j without i, then the six-shell fma chain.
+template <class Real>
+__device__ __forceinline__ double eval_box6(const uint8_t *box, int k, int V, int S, const Real *D1,
+                                            const Real *D2, const Real *Dx, const Real *e0, Real nu,
+                                            Real kT, int &A_out, Real &ea_out) {
+  const int dk = dir_sx(k) + 11 * dir_sy(k) + 121 * dir_sz(k);
+  const int jb = kBoxCF + dk;
+  const int a4 = box[jb];
+  const int A = a4 >> 2;
+  A_out = A;
+  ea_out = Real(__builtin_huge_valf());
+  if (A == V) return 0.0;
+  uint64_t ci[6] = {0, 0, 0, 0, 0, 0}, cj[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 8
+  for (int m = 0; m < kObsN; ++m) {
+    const int off = kBondFar.off[m];
+    const int sh = kBondFar.sh[m];
+    // bytes hold 4*species: << 1 gives 8*species
+    const uint64_t bi = 1ull << (box[kBoxCF + off] << 1);
+    const uint64_t bj = 1ull << (box[jb + off] << 1);
+    if (off != dk) ci[sh] += bi;
+    if (off != -dk) cj[sh] += bj;
+  }
+  const Real de = delta_e_counts6<Real>(ci, cj, S, D1 + 8 * A, D2 + 8 * A, Dx, A);
+  const Real ea = e0[A] + Real(0.5) * de;
+  ea_out = ea;
+  return (double)rate_from_barrier(ea, nu, kT);
+}
+
 // LDS of the learned barrier (one group per block): bf16 weights, the
 // 64-row code staging, the activation staging tile, outputs, biases and
 // output weights, the one-hot input tile.
@@ -221,12 +319,16 @@ __host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
 
 // KL: the most tree levels of any lattice of the launch (at most
 // kMaxLevels); the level loops are unrolled that far.
-// LRN: the learned runtime forms (policy selection, Poisson time), one
-// 64-lane group per launch.
-template <int G, class Real, bool MLP = false, int KL = kMaxLevels, bool LRN = false>
+// LRN: the learned runtime forms (policy selection, Poisson time); FAR: the
+// pair model out to 6.0 A; both with one 64-lane group per launch.
+template <int G, class Real, bool MLP = false, int KL = kMaxLevels, bool LRN = false, bool FAR = false>
 struct Runner {
-  static constexpr int FN = LRN ? kFootNL : kFootN;  // gather elements per box
-  static constexpr int FM = LRN ? 9 : 8;             // gather elements per lane and pass
+  // gather elements per box (the sites and the vacancy itself), per lane
+  // and pass (G/8 boxes), box bytes, reach of a jump's changes in half-cells
+  static constexpr int FN = FAR ? kFootFarN + 1 : LRN ? kFootNL : kFootN;
+  static constexpr int FM = (FN + 7) / 8;
+  static constexpr int BB = FAR ? kBoxBytesFar : kBoxBytes;
+  static constexpr int REACH = FAR ? 6 : LRN ? 5 : 4;
   LoopArgs a;
   Group<G> gp;
   int foot[FM];
@@ -431,7 +533,7 @@ struct Runner {
   // Learned-barrier rates of one refresh pass (all 64 lanes take part in the
   // matrix-core forward; lane q*8+k owns candidate k of pass slot q).
   __device__ double eval_mlp_pass(int np, int q, int k, int p0, int &vv) {
-    const uint8_t *box = s.box + q * kBoxBytes;
+    const uint8_t *box = s.box + q * BB;
     int A = V;
     bool ood = false;
     float ea_pair = 0.f;
@@ -542,7 +644,7 @@ struct Runner {
         uint8_t v8 = val[m];
         if (site[m] == si) v8 = (uint8_t)a_new;
         else if (site[m] == sj) v8 = (uint8_t)V;
-        s.box[fe_q(f) * kBoxBytes + fe_byte(f)] = (uint8_t)(v8 << 2);
+        s.box[fe_q(f) * BB + fe_byte(f)] = (uint8_t)(v8 << 2);
       }
       gsync();
       const int q = gp.gl >> 3, k = gp.gl & 7;
@@ -553,7 +655,10 @@ struct Runner {
           vv = s.aff[p0 + q];
           int A;
           Real ea;
-          r = eval_box<Real>(s.box + q * kBoxBytes, k, V, s.D1, s.D2, s.e0, nu, kT, A, ea);
+          if (FAR)
+            r = eval_box6<Real>(s.box + q * BB, k, V, S, s.D1, s.D2, s.Dx, s.e0, nu, kT, A, ea);
+          else
+            r = eval_box<Real>(s.box + q * BB, k, V, s.D1, s.D2, s.e0, nu, kT, A, ea);
           s.spec[vv * 8 + k] = (uint8_t)A;
           if (eat) eat[vv * 8 + k] = ea;
         }
@@ -578,7 +683,7 @@ struct Runner {
     const int gl = gp.gl;
     const double pfx = subgroup_prefix(r, k);
     if (q < np && k == 7) pg[vv] = pfx;
-    for (int qq = 0; qq < np; ++qq) obs[qq * kObsN + gl] = s.box[qq * kBoxBytes + kObsSrc.b[gl]] >> 2;
+    for (int qq = 0; qq < np; ++qq) obs[qq * kObsN + gl] = s.box[qq * BB + kObsSrc.b[gl]] >> 2;
     gsync();
     for (int qq = 0; qq < np; ++qq) {
       const int v_q = s.aff[p0 + qq];
@@ -681,6 +786,8 @@ struct Runner {
       s.D2[x] = fp32 ? (Real)d->D2f[x] : (Real)d->D2[x];
     }
     if (gl < 8) s.e0[gl] = fp32 ? (Real)d->e0f[gl] : (Real)d->e0[gl];
+    if (FAR)
+      for (int x = gl; x < 256; x += G) s.Dx[x] = fp32 ? (Real)(&d->Dxf[0][0])[x] : (Real)(&d->Dx[0][0])[x];
     nu = fp32 ? (Real)d->nuf : (Real)d->nu;
     kT = fp32 ? (Real)d->kTf : (Real)d->kT;
     const uint64_t seed = d->seed, stream = d->stream;
@@ -890,9 +997,9 @@ struct Runner {
             dy = min(dy, g.Y2 - dy);
             dz = min(dz, g.Z2 - dz);
             // reach: a candidate's bonds lie within 3 half-cells of its
-            // vacancy, an observation within 4, so i or j changes them only
-            // within 4 (5) half-cells of i
-            hit[u] = b0 + u * G + gl < nv && max(dx, max(dy, dz)) <= (LRN ? 5 : 4);
+            // vacancy (5 with pairs out to 6.0 A), an observation within 4,
+            // so i or j changes them only within REACH half-cells of i
+            hit[u] = b0 + u * G + gl < nv && max(dx, max(dy, dz)) <= REACH;
           }
         };
         bool others = false;
@@ -947,7 +1054,10 @@ struct Runner {
         if (gl < 8) {
           int Ak;
           Real ea;
-          r = eval_box<Real>(s.box, kk, V, s.D1, s.D2, s.e0, nu, kT, Ak, ea);
+          if (FAR)
+            r = eval_box6<Real>(s.box, kk, V, S, s.D1, s.D2, s.Dx, s.e0, nu, kT, Ak, ea);
+          else
+            r = eval_box<Real>(s.box, kk, V, s.D1, s.D2, s.e0, nu, kT, Ak, ea);
           s.spec[v * 8 + kk] = (uint8_t)Ak;
           if (eat) eat[v * 8 + kk] = ea;
         }
@@ -994,7 +1104,8 @@ struct Runner {
   }
 };
 
-template <int G, int WAVES, bool FP32, bool MLP = false, int KL = kMaxLevels, bool LRN = false>
+template <int G, int WAVES, bool FP32, bool MLP = false, int KL = kMaxLevels, bool LRN = false,
+          bool FAR = false>
 __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayout L) {
   using Real = typename std::conditional<FP32, float, double>::type;
   extern __shared__ __align__(16) unsigned char lds[];
@@ -1009,7 +1120,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayo
   // This lane's share of the footprint gathers: element f = gl + G*m of the
   // (G/8) boxes of a refresh pass, packed as described at fe_dx (box byte,
   // offsets, box number q, centre and far flags); -1 if none.
-  using Run = Runner<G, Real, MLP, KL, LRN>;
+  using Run = Runner<G, Real, MLP, KL, LRN, FAR>;
   constexpr int FN = Run::FN, FM = Run::FM;
   int foot[FM];
   constexpr int P = G / 8;
@@ -1021,17 +1132,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayo
       continue;
     }
     const int q = f / FN, e = f % FN;
-    if (e == FN - 1) {
-      foot[m] = kBoxC | (4 << 9) | (4 << 13) | (4 << 17) | (q << 21) | (1 << 27);
+    if (FAR) {
+      if (e == FN - 1) {
+        foot[m] = fe_pack(kBoxCF, 0, 0, 0, q, true, false);
+      } else {
+        const int dx = kFootFar.d[e][0], dy = kFootFar.d[e][1], dz = kFootFar.d[e][2];
+        foot[m] = fe_pack((dx + 5) + 11 * (dy + 5) + 121 * (dz + 5), dx, dy, dz, q, false, false);
+      }
+    } else if (e == FN - 1) {
+      foot[m] = fe_pack(kBoxC, 0, 0, 0, q, true, false);
     } else if (e >= kFootN - 1) {
       const int fi = e - (kFootN - 1);  // order of kFarD: -x, -y, -z, +z, +y, +x
       const int axis = fi < 3 ? fi : 5 - fi, len = fi < 3 ? -4 : 4;
       const int dx = axis == 0 ? len : 0, dy = axis == 1 ? len : 0, dz = axis == 2 ? len : 0;
-      foot[m] = fi | ((dx + 4) << 9) | ((dy + 4) << 13) | ((dz + 4) << 17) | (q << 21) | (1 << 28);
+      foot[m] = fe_pack(fi, dx, dy, dz, q, false, true);
     } else {
       const int dx = kFoot.d[e][0], dy = kFoot.d[e][1], dz = kFoot.d[e][2];
-      const int bi = (dx + 3) + 7 * (dy + 3) + 49 * (dz + 3);
-      foot[m] = bi | ((dx + 4) << 9) | ((dy + 4) << 13) | ((dz + 4) << 17) | (q << 21);
+      foot[m] = fe_pack((dx + 3) + 7 * (dy + 3) + 49 * (dz + 3), dx, dy, dz, q, false, false);
     }
   }
 
@@ -1114,6 +1231,32 @@ hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_spec
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(1), dim3(64), lds, stream, b, L);
   return hipGetLastError();
+}
+
+size_t event_loop_far_lds_bytes(int nv_max, int precision) {
+  return (size_t)make_layout(nv_max, 64, precision == AKMC_FP32, 1).bytes;
+}
+
+template <bool FP32>
+static hipError_t launch_far(const LoopArgs &a, hipStream_t stream) {
+  const GroupLayout L = make_layout(a.nv_max, 64, FP32 ? 1 : 0, 1);
+  auto kern = L.nlev_max <= 2 ? k_event_loop<64, 1, FP32, false, 2, false, true>
+                              : k_event_loop<64, 1, FP32, false, 3, false, true>;
+  const size_t lds = (size_t)L.bytes;
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(kern, dim3(1), dim3(64), lds, stream, a, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_event_loop_far(const LoopArgs &a, int precision, int refresh_full, hipStream_t stream) {
+  LoopArgs b = a;
+  b.refresh_full = refresh_full;
+  hipError_t e = launch_queue_reset(a.queue, stream);
+  if (e != hipSuccess) return e;
+  return precision == AKMC_FP32 ? launch_far<true>(b, stream) : launch_far<false>(b, stream);
 }
 
 size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3],

@@ -22,6 +22,7 @@
 
 #include "akmc_device.hpp"
 #include "akmc_internal.hpp"
+#include "akmc_patch.hpp"
 
 namespace akmc {
 
@@ -47,6 +48,14 @@ template <> struct Tab<float> {
   __device__ static float nu(const LatDesc *d) { return d->nuf; }
   __device__ static float kT(const LatDesc *d) { return d->kTf; }
   __device__ static float beta(const LatDesc *d) { return d->betaf; }
+};
+
+template <class Real> struct TabFar;
+template <> struct TabFar<double> {
+  __device__ static const double *Dx(const LatDesc *d) { return &d->Dx[0][0]; }
+};
+template <> struct TabFar<float> {
+  __device__ static const float *Dx(const LatDesc *d) { return &d->Dxf[0][0]; }
 };
 
 template <class Real> __device__ __forceinline__ Real inf_of();
@@ -106,6 +115,90 @@ __global__ __launch_bounds__(256) void k_rates_sites(const LatDesc *__restrict__
     c1i -= onehot(A);           // N1(i) without j
     c1j -= onehot(occ[i]);      // N1(j) without i
     de = delta_e_counts<Real>(c1i, c1j, c2i, c2j, sD1 + 8 * A, sD2 + 8 * A);
+    e = se0[A] + Real(0.5) * de;
+    r = rate_from_barrier(e, Tab<Real>::nu(d), Tab<Real>::kT(d));
+  }
+  rates[c] = r;
+  if (ea) ea[c] = e;
+  if (de_out) de_out[c] = de;
+}
+
+// ------------------------------------------- pair model out to 6.0 A
+
+// The 64 neighbours within 6.0 A with their shell (0..5), in the order of
+// the observation (by length, then x, y, z).
+struct Shell64 {
+  int8_t d[kObsN][3];
+  int8_t sh[kObsN];
+};
+constexpr Shell64 make_shell64() {
+  Shell64 r{};
+  const ObsTab t = make_obs();
+  for (int m = 0; m < kObsN; ++m) {
+    const int dx = t.d[m][0], dy = t.d[m][1], dz = t.d[m][2];
+    const int r2 = dx * dx + dy * dy + dz * dz;
+    r.d[m][0] = t.d[m][0];
+    r.d[m][1] = t.d[m][1];
+    r.d[m][2] = t.d[m][2];
+    r.sh[m] = (int8_t)(r2 == 3 ? 0 : r2 == 4 ? 1 : r2 == 8 ? 2 : r2 == 11 ? 3 : r2 == 12 ? 4 : 5);
+  }
+  return r;
+}
+__constant__ Shell64 kShell64 = make_shell64();
+
+// One thread per candidate of a site list, bond counts gathered straight
+// from the occupancy (all six shells of i and of j = the target), the same
+// arithmetic as the event loop's six-shell evaluation.
+template <class Real>
+__global__ __launch_bounds__(256) void k_rates_sites_far(const LatDesc *__restrict__ d,
+                                                         const uint8_t *__restrict__ occ,
+                                                         const int32_t *__restrict__ sites,
+                                                         int64_t n_sites, Real *__restrict__ rates,
+                                                         Real *__restrict__ ea, Real *__restrict__ de_out) {
+  __shared__ Real sD1[64], sD2[64], sDx[256], se0[8];
+  const int tid = threadIdx.x;
+  if (tid < 64) { sD1[tid] = Tab<Real>::D1(d)[tid]; sD2[tid] = Tab<Real>::D2(d)[tid]; }
+  sDx[tid] = TabFar<Real>::Dx(d)[tid];
+  if (tid < 8) se0[tid] = Tab<Real>::e0(d)[tid];
+  __syncthreads();
+  const int64_t c = (int64_t)blockIdx.x * 256 + tid;
+  if (c >= n_sites * 8) return;
+  const int64_t a = c >> 3;
+  const int k = (int)(c & 7);
+  const Geo g = make_geo(d->lx, d->ly, d->lz);
+  const int S = d->S, V = S - 1;
+  const int i = sites ? sites[a] : (int)a;
+  if (i < 0 || i >= 2 * g.ncell) {
+    rates[c] = Real(__builtin_nan(""));
+    if (ea) ea[c] = Real(__builtin_nan(""));
+    if (de_out) de_out[c] = Real(__builtin_nan(""));
+    return;
+  }
+  int X, Y, Z;
+  pos_of(g, i, X, Y, Z);
+  const int kx = dir_sx(k), ky = dir_sy(k), kz = dir_sz(k);
+  const int JX = wrapc(X + kx, g.X2), JY = wrapc(Y + ky, g.Y2), JZ = wrapc(Z + kz, g.Z2);
+  const int A = occ[site_of(g, JX, JY, JZ)];
+  Real r, e, de = Real(__builtin_nan(""));
+  if (A == V) {
+    r = Real(0);
+    e = inf_of<Real>();
+  } else {
+    uint64_t ci[6] = {0, 0, 0, 0, 0, 0}, cj[6] = {0, 0, 0, 0, 0, 0};
+    for (int m = 0; m < kObsN; ++m) {
+      const int dx = kShell64.d[m][0], dy = kShell64.d[m][1], dz = kShell64.d[m][2];
+      const int sh = kShell64.sh[m];
+      // neighbour of i (skip j itself) and of j (skip i itself)
+      if (!(dx == kx && dy == ky && dz == kz)) {
+        const int si = occ[site_of(g, wrapc(X + dx, g.X2), wrapc(Y + dy, g.Y2), wrapc(Z + dz, g.Z2))];
+        ci[sh] += 1ull << (8 * si);
+      }
+      if (!(dx == -kx && dy == -ky && dz == -kz)) {
+        const int sj = occ[site_of(g, wrapc(JX + dx, g.X2), wrapc(JY + dy, g.Y2), wrapc(JZ + dz, g.Z2))];
+        cj[sh] += 1ull << (8 * sj);
+      }
+    }
+    de = delta_e_counts6<Real>(ci, cj, S, sD1 + 8 * A, sD2 + 8 * A, sDx, A);
     e = se0[A] + Real(0.5) * de;
     r = rate_from_barrier(e, Tab<Real>::nu(d), Tab<Real>::kT(d));
   }
@@ -544,6 +637,15 @@ hipError_t launch_rates_sites(const LatDesc *d_desc, const LatDesc &h, const uin
   if (n_sites <= 0) return hipSuccess;
   const int64_t nthreads = n_sites * 8;
   const unsigned blocks = (unsigned)((nthreads + 255) / 256);
+  if (h.n_shells == 6) {
+    if (precision == AKMC_FP32)
+      launch_timed(k_rates_sites_far<float>, dim3(blocks), dim3(256), 0, stream, tm, d_desc, occ, sites,
+                   n_sites, (float *)rates, (float *)ea, (float *)de);
+    else
+      launch_timed(k_rates_sites_far<double>, dim3(blocks), dim3(256), 0, stream, tm, d_desc, occ, sites,
+                   n_sites, (double *)rates, (double *)ea, (double *)de);
+    return hipGetLastError();
+  }
   if (precision == AKMC_FP32)
     launch_timed(k_rates_sites<float>, dim3(blocks), dim3(256), 0, stream, tm, d_desc, occ, sites,
                  n_sites, (float *)rates, (float *)ea, (float *)de);
@@ -597,6 +699,9 @@ static hipError_t launch_sweep_r(const LatDesc *d_desc, const LatDesc &h, const 
 hipError_t launch_rates_all(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                             int precision, void *rates, void *ea, hipStream_t stream,
                             const LaunchTiming *tm) {
+  // The six-shell model takes the per-candidate kernel over every site.
+  if (h.n_shells == 6)
+    return launch_rates_sites(d_desc, h, occ, nullptr, 2 * h.ncell, precision, rates, ea, stream, tm);
   if (precision == AKMC_FP32) return launch_sweep_r<float>(d_desc, h, occ, rates, ea, stream, tm);
   // The binary64 sweep's factors must stay inside the exponent range; tables
   // that could leave it take the per-candidate kernel over every site.

@@ -68,7 +68,8 @@ def test_create_rejects_null_and_bad_codes_without_gpu():
 
 def test_struct_sizes_match_header():
     assert C.sizeof(akmc.Event) == 40
-    assert C.sizeof(akmc.Params) == 4 * 4 + 8 * (64 + 64 + 8) + 8 * 3 + 8 * 2 + 8 * 3 + 4 * 4
+    assert C.sizeof(akmc.Params) == (4 * 4 + 8 * (64 + 64 + 8) + 8 * 3 + 8 * 2 + 8 * 3 + 4 * 4
+                                     + 4 * 2 + 8 * 4 * 64)
 
 
 def test_null_handles_are_rejected_without_gpu():
@@ -90,7 +91,40 @@ def test_null_handles_are_rejected_without_gpu():
         lambda: L.akmc_batch_autotune(None, 1, None),
         lambda: L.akmc_batch_state_read(None, 0, None, None, None),
         lambda: L.akmc_batch_destroy(None),
+        lambda: L.akmc_cluster_hist_noalloc(None, 1, 8, None),
+        lambda: L.akmc_kmc_run_until(None, 1.0, 1, None),
+        lambda: L.akmc_batch_priority(None, None, None),
+        lambda: L.akmc_batch_run_until(None, 1.0, 1, 0),
+        lambda: L.akmc_patchnet_eval(None, None, None, 0, None),
+        lambda: L.akmc_policy_attach(None, None, 1.0),
+        lambda: L.akmc_poisson_attach(None, None),
+        lambda: L.akmc_patchnet_blob_bytes(5, 0, 8, None),
+        lambda: L.akmc_patchnet_blob_bytes(5, 16, 3, None),
+        lambda: L.akmc_voxel_grid(None, 1, 1, 0.6, 1e-4, 0.1, None, None, None, None),
     ]
     for call in calls:
         assert call() == akmc.ERR_INVALID
         assert akmc.last_error()
+
+
+def test_params_checks_of_the_far_pair_model():
+    """n_shells must be 2 or 6; the six-shell model needs edges of 5 cells
+    and symmetric far tables (host-side checks, no GPU)."""
+    spec = W.random_lattice(np.random.default_rng(3), (5, 5, 5), 4, 2)
+    spec.eps_far = W.far_tables(np.random.default_rng(4), 4)
+    p = akmc.make_params(spec)
+    assert p.n_shells == 6 and akmc.workspace_bytes(p, 2) > 0
+    bad = akmc.make_params(spec)
+    bad.n_shells = 3
+    with pytest.raises(akmc.AkmcError):
+        akmc.workspace_bytes(bad, 2)
+    bad = akmc.make_params(spec)
+    bad.eps_far[2][1] += 0.01
+    with pytest.raises(akmc.AkmcError) as e:
+        akmc.workspace_bytes(bad, 2)
+    assert "symmetric" in str(e.value)
+    small = W.random_lattice(np.random.default_rng(5), (4, 5, 5), 4, 2)
+    small.eps_far = spec.eps_far
+    with pytest.raises(akmc.AkmcError) as e:
+        akmc.workspace_bytes(akmc.make_params(small), 2)
+    assert "5 cells" in str(e.value)
