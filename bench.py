@@ -291,7 +291,38 @@ def bench_forms(args, torch, akmc, W, stream):
         forms["voxel_ensemble"] = bench_voxels(args, torch, akmc, W, stream)
     if args.learned_events > 0:
         forms["learned_runtime"] = bench_learned(args, torch, akmc, W, stream)
+    if args.far_events > 0:
+        forms["pairs_to_6A"] = bench_far(args, torch, akmc, W, stream)
     return forms
+
+
+def bench_far(args, torch, akmc, W, stream):
+    """The costlier energy model: pair energies out to 6.0 A (six shells,
+    126 changed bonds per jump instead of 26) on the 4.2M-site lattice,
+    binary32 rates: event loop events/s and the rate evaluation of every
+    site (the per-candidate kernel)."""
+    spec = W.rpv_4m_far()
+    lat = akmc.Lattice(spec, precision=akmc.FP32, stream=stream)
+    out = torch.empty((spec.n_sites, 8), dtype=torch.float32, device="cuda")
+    with torch.cuda.stream(stream):
+        lat.step(2000)
+        akmc.rates_eval(lat.h, akmc.RATES_ALL_SITES, None, 0, out)
+        torch.cuda.synchronize()
+        a0, a1, a2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a0.record(stream)
+        lat.step(args.far_events)
+        a1.record(stream)
+        for _ in range(3):
+            akmc.rates_eval(lat.h, akmc.RATES_ALL_SITES, None, 0, out)
+        a2.record(stream)
+        torch.cuda.synchronize()
+    loop_s = a0.elapsed_time(a1) * 1e-3
+    sweep_s = a1.elapsed_time(a2) * 1e-3 / 3
+    lat.close()
+    return {"shells": 6, "bonds_per_jump": 126, "events": args.far_events,
+            "events_per_s": args.far_events / loop_s, "us_per_event": loop_s * 1e6 / args.far_events,
+            "all_sites_rate_evals_per_s": spec.n_sites * 8 / sweep_s,
+            "all_sites_ms": sweep_s * 1e3}
 
 
 def bench_voxels(args, torch, akmc, W, stream):
@@ -519,6 +550,8 @@ def main():
     ap.add_argument("--voxel-blocks", type=int, default=128, help="persistent groups of the ensemble")
     ap.add_argument("--learned-events", type=int, default=20_000,
                     help="events per form of the learned runtime (0 = skip)")
+    ap.add_argument("--far-events", type=int, default=20_000,
+                    help="events of the pair model out to 6.0 A (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one elementwise pass over 256 MiB (reads 256 MiB, writes "
                          "256 MiB): the reference for the HBM byte counters")

@@ -368,7 +368,7 @@ akmc_status akmc_batch_run_until(akmc_batch b, double t_end, int64_t max_events_
  * sites within 6.0 A, the neighbour cap of Sec. IV-C; BCC shells 1-6, the
  * m-th neighbour being the m-th offset ordered by length, then x, y, z).
  * Network (the paper gives no architecture; this is the library's): hidden
- * width H <= 64, n_out outputs,
+ * width H a multiple of 8 up to 64, n_out outputs,
  *   h1 = relu(b1 + sum_m W1[m][code_m])          (m = 0..63, binary32 adds)
  *   h2 = relu(b2 + sum_i h1[i] W2[i][:])          (binary32 fma, i ascending)
  *   out = b3 + sum_i h2[i] W3[i][:]                (binary32 fma, i ascending)
@@ -393,8 +393,8 @@ akmc_status akmc_patchnet_blob_bytes(int32_t n_species, int32_t hidden, int32_t 
  * host_params binary32 [W1 (64*S*H, [m][s][j]), b1 (H), W2 (H*H, [i][j]),
  * b2 (H), W3 (H*n_out, [i][k]), b3 (n_out)]; the weights are rounded to
  * bfloat16 (to nearest, ties to even), the biases kept.  Errors: INVALID
- * (S not in [2, 8], H not in [1, 64], n_out not 1 or 8, NULL, non-finite
- * values), HIP. */
+ * (S not in [2, 8], H not a multiple of 8 in [8, 64], n_out not 1 or 8,
+ * NULL, non-finite values), HIP. */
 akmc_status akmc_patchnet_set(void *d_blob, int32_t n_species, int32_t hidden, int32_t n_out,
                               const float *host_params);
 

@@ -1215,7 +1215,8 @@ akmc_status akmc_voxel_grid(const double *T, int32_t nx, int32_t nz, double e_ef
 
 akmc_status akmc_patchnet_blob_bytes(int32_t n_species, int32_t hidden, int32_t n_out, size_t *bytes) {
   if (n_species < 2 || n_species > AKMC_MAX_SPECIES) return fail(AKMC_ERR_INVALID, "n_species must lie in [2, 8]");
-  if (hidden < 1 || hidden > kPatchMaxHidden) return fail(AKMC_ERR_INVALID, "hidden must lie in [1, 64]");
+  if (hidden < 8 || hidden > kPatchMaxHidden || hidden % 8 != 0)
+    return fail(AKMC_ERR_INVALID, "hidden must be a multiple of 8 in [8, 64]");
   if (n_out != 1 && n_out != 8) return fail(AKMC_ERR_INVALID, "n_out must be 1 (Poisson) or 8 (policy)");
   if (!bytes) return fail(AKMC_ERR_INVALID, "bytes is NULL");
   *bytes = patch_layout(n_species, hidden, n_out).total;
@@ -1262,8 +1263,8 @@ akmc_status akmc_patchnet_set(void *d_blob, int32_t n_species, int32_t hidden, i
 static akmc_status read_patch_header(const void *d_blob, PatchHeader *hdr) {
   if (!d_blob) return fail(AKMC_ERR_INVALID, "blob is NULL");
   HIP_TRY(hipMemcpy(hdr, d_blob, sizeof(PatchHeader), hipMemcpyDeviceToHost));
-  if (hdr->magic != kPatchMagic || hdr->S < 2 || hdr->S > AKMC_MAX_SPECIES || hdr->H < 1 ||
-      hdr->H > kPatchMaxHidden || (hdr->n_out != 1 && hdr->n_out != 8))
+  if (hdr->magic != kPatchMagic || hdr->S < 2 || hdr->S > AKMC_MAX_SPECIES || hdr->H < 8 ||
+      hdr->H > kPatchMaxHidden || hdr->H % 8 != 0 || (hdr->n_out != 1 && hdr->n_out != 8))
     return fail(AKMC_ERR_INVALID, "not a network blob written by akmc_patchnet_set");
   return AKMC_OK;
 }

@@ -154,7 +154,8 @@ constexpr BondFar make_bond_far() {
   }
   return r;
 }
-__constant__ BondFar kBondFar = make_bond_far();
+// Used in fully unrolled loops only, so every entry folds into an immediate.
+constexpr BondFar kBondFar = make_bond_far();
 
 // Box byte of each observation neighbour: inside the 7x7x7 box, or the far
 // slot of an axis site 4 half-cells away.
@@ -285,7 +286,7 @@ __device__ __forceinline__ double eval_box6(const uint8_t *box, int k, int V, in
   ea_out = Real(__builtin_huge_valf());
   if (A == V) return 0.0;
   uint64_t ci[6] = {0, 0, 0, 0, 0, 0}, cj[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll 8
+#pragma unroll
   for (int m = 0; m < kObsN; ++m) {
     const int off = kBondFar.off[m];
     const int sh = kBondFar.sh[m];
@@ -359,6 +360,7 @@ struct Runner {
   double *wq;     // [64] selection weights of one refresh pass, lane order
   uint8_t *obs;   // [8][64] observation codes of one refresh pass
   float *hbuf;    // [64] activation staging
+  int obs_src;    // box byte of this lane's observation neighbour
 
   __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
                     const int (&foot_)[FM], unsigned char *lds)
@@ -376,6 +378,7 @@ struct Runner {
       b = obs + 8 * kObsN;
       has_pol = a.pol_blob != nullptr;
       has_pt = a.pt_blob != nullptr;
+      obs_src = kObsSrc.b[gp.gl];
       inv_tau = a.inv_tau;
       if (has_pol) {
         pol = patch_stage(a.pol_blob, b, gp.gl, G);
@@ -683,7 +686,7 @@ struct Runner {
     const int gl = gp.gl;
     const double pfx = subgroup_prefix(r, k);
     if (q < np && k == 7) pg[vv] = pfx;
-    for (int qq = 0; qq < np; ++qq) obs[qq * kObsN + gl] = s.box[qq * BB + kObsSrc.b[gl]] >> 2;
+    for (int qq = 0; qq < np; ++qq) obs[qq * kObsN + gl] = s.box[qq * BB + obs_src] >> 2;
     gsync();
     for (int qq = 0; qq < np; ++qq) {
       const int v_q = s.aff[p0 + qq];
@@ -757,15 +760,30 @@ struct Runner {
     return Q(nlev)[nl(nlev) - 1];
   }
 
+  // x of lane 15 of the previous 16-lane row (DPP row_bcast:15; rows in
+  // row_mask only, the others receive 0), and of lane 31 (row_bcast:31).
+  template <int CTRL, int ROWS>
+  __device__ __forceinline__ static double row_bcast(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+  }
+
   // Sum of a per-slot array in an order fixed by nv alone: lane l adds
-  // slots l, l + 64, ... in turn, then a butterfly over the 64 lanes (every
-  // lane ends with the same value).  64-lane groups only.
+  // slots l, l + 64, ... in turn; each 16-lane row is summed by a
+  // Kogge-Stone scan over DPP row shifts, the row totals are added by row
+  // broadcasts (rows 0+1, 2+3, then both halves) and lane 63's total is
+  // returned to every lane.  64-lane groups only.
   __device__ double slot_sum(const double *x) const {
     double acc = 0.0;
     for (int v = gp.gl; v < nv; v += 64) acc += x[v];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-    return acc;
+    acc += row_shr<1>(acc);
+    acc += row_shr<2>(acc);
+    acc += row_shr<4>(acc);
+    acc += row_shr<8>(acc);
+    acc += row_bcast<0x142, 0xA>(acc);
+    acc += row_bcast<0x143, 0xC>(acc);
+    return lane_value(acc, 63);
   }
 
   __device__ void run(int lat) {

@@ -8,7 +8,7 @@
 // 24, 8, 6 sites), neighbour m being the m-th offset (in a/2 units) ordered
 // by squared length, then x, y, z ascending.
 //
-// Network (hidden width H <= 64, n_out outputs: 8 logits for the policy, 1
+// Network (hidden width H a multiple of 8 up to 64, n_out outputs: 8 logits for the policy, 1
 // value for the Poisson network), binary32 arithmetic on bfloat16 weights:
 //   h1[j] = relu(b1[j] + sum_m W1[m][code_m][j])            (m = 0..63 in order)
 //   h2[j] = relu(b2[j] + sum_i h1[i] W2[i][j])              (one fma per i, ascending)
@@ -96,15 +96,22 @@ __host__ __device__ inline PatchLayout patch_layout(int S, int H, int n_out) {
   return L;
 }
 
-// LDS bytes of one staged network: bf16 W1, W2, W3 and binary32 biases.
+// Staged layout in LDS: W1 as in the blob ([64][S][H], lane j reads
+// element j of a row), W2 and W3 transposed ([j][i] and [k][i], rows padded
+// by 16 bytes) so that lane j reads its own 64 weights as eight 16-byte
+// vectors, then the binary32 biases.
+__host__ __device__ inline int patch_w1_elems(int S, int H) { return kObsN * S * H; }
+// bf16 elements per transposed row: H rounded up to 8 (16-byte aligned rows),
+// plus 8 of padding
+__host__ __device__ inline int patch_ldt(int H) { return ((H + 7) & ~7) + 8; }
 __host__ __device__ inline int patch_lds_bytes(int S, int H, int n_out) {
-  const int w = 2 * (kObsN * S * H + H * H + H * n_out);
+  const int w = 2 * (patch_w1_elems(S, H) + (H + n_out) * patch_ldt(H));
   return ((w + 15) & ~15) + 4 * ((2 * H + n_out + 3) & ~3);
 }
 
 // A network staged in LDS.
 struct PatchNet {
-  const unsigned short *w1, *w2, *w3;
+  const unsigned short *w1, *w2t, *w3t;
   const float *b1, *b2, *b3;
   int S, H, n_out;
 };
@@ -119,13 +126,20 @@ __device__ inline PatchNet patch_stage(const unsigned char *blob, unsigned char 
   const int S = h->S, H = h->H, no = h->n_out;
   const PatchLayout L = patch_layout(S, H, no);
   const float *p = (const float *)(blob + L.params);
+  const int ld = patch_ldt(H);
   unsigned short *w = (unsigned short *)dst;
-  const int nw1 = kObsN * S * H, nw2 = H * H, nw3 = H * no;
+  const int nw1 = patch_w1_elems(S, H);
+  unsigned short *w2t = w + nw1, *w3t = w2t + H * ld;
   for (int x = tid; x < nw1; x += nthreads) w[x] = (unsigned short)(__float_as_uint(p[L.oW1 + x]) >> 16);
-  for (int x = tid; x < nw2; x += nthreads) w[nw1 + x] = (unsigned short)(__float_as_uint(p[L.oW2 + x]) >> 16);
-  for (int x = tid; x < nw3; x += nthreads)
-    w[nw1 + nw2 + x] = (unsigned short)(__float_as_uint(p[L.oW3 + x]) >> 16);
-  float *b = (float *)(dst + ((2 * (nw1 + nw2 + nw3) + 15) & ~15));
+  for (int x = tid; x < H * H; x += nthreads) {
+    const int i = x / H, j = x - i * H;  // W2[i][j] -> row j, column i
+    w2t[j * ld + i] = (unsigned short)(__float_as_uint(p[L.oW2 + x]) >> 16);
+  }
+  for (int x = tid; x < H * no; x += nthreads) {
+    const int i = x / no, k = x - i * no;  // W3[i][k] -> row k, column i
+    w3t[k * ld + i] = (unsigned short)(__float_as_uint(p[L.oW3 + x]) >> 16);
+  }
+  float *b = (float *)(dst + ((2 * (nw1 + (H + no) * ld) + 15) & ~15));
   for (int x = tid; x < H; x += nthreads) {
     b[x] = p[L.ob1 + x];
     b[H + x] = p[L.ob2 + x];
@@ -133,8 +147,8 @@ __device__ inline PatchNet patch_stage(const unsigned char *blob, unsigned char 
   for (int x = tid; x < no; x += nthreads) b[2 * H + x] = p[L.ob3 + x];
   PatchNet n;
   n.w1 = w;
-  n.w2 = w + nw1;
-  n.w3 = w + nw1 + nw2;
+  n.w2t = w2t;
+  n.w3t = w3t;
   n.b1 = b;
   n.b2 = b + H;
   n.b3 = b + 2 * H;
@@ -154,31 +168,63 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Forward of one observation (codes[0..63] in LDS, species codes < S) by
-// one full wavefront; hbuf is a 64-float LDS staging area.  Lane k < n_out
-// returns output k (other lanes return 0).  Every lane must take part.
+// sum_i x[i] * w[i] for i = 0 .. H-1 in ascending order (one fma each),
+// starting from acc (H a multiple of 8): x is the 64-float activation
+// staging (read as 16-byte vectors, the same address in every lane), w a
+// bf16 row of 16-byte aligned chunks.
+__device__ __forceinline__ float patch_dot(const float *x, const unsigned short *w, int H, float acc) {
+  for (int i0 = 0; i0 < H; i0 += 8) {
+    const uint4 wv = *(const uint4 *)(w + i0);
+    const float4 xa = *(const float4 *)(x + i0);
+    const float4 xb = *(const float4 *)(x + i0 + 4);
+    const uint32_t wr[4] = {wv.x, wv.y, wv.z, wv.w};
+    const float xs[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t word = wr[e >> 1];
+      const float we = __uint_as_float((e & 1) ? (word & 0xFFFF0000u) : (word << 16));
+      acc = fmaf(xs[e], we, acc);
+    }
+  }
+  return acc;
+}
+
+// Forward of one observation (codes[0..63] in LDS, 16-byte aligned, species
+// codes < S) by one full wavefront; hbuf is a 64-float, 16-byte aligned LDS
+// staging area.  Lane k < n_out returns output k (other lanes return 0).
+// Every lane must take part.
 __device__ inline float patch_forward(const PatchNet &n, const uint8_t *codes, float *hbuf, int lane) {
   const int H = n.H, S = n.S;
   const int j = lane < H ? lane : H - 1;
+  // all 64 codes in scalar registers (the same 64 bytes in every lane), so
+  // that each row offset is scalar arithmetic
+  uint32_t cw[16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint4 v = *(const uint4 *)(codes + 16 * q);
+    cw[4 * q] = __builtin_amdgcn_readfirstlane(v.x);
+    cw[4 * q + 1] = __builtin_amdgcn_readfirstlane(v.y);
+    cw[4 * q + 2] = __builtin_amdgcn_readfirstlane(v.z);
+    cw[4 * q + 3] = __builtin_amdgcn_readfirstlane(v.w);
+  }
   float acc = n.b1[j];
-#pragma unroll 16
+  const unsigned short *w1 = n.w1 + j;
+#pragma unroll
   for (int m = 0; m < kObsN; ++m) {
-    const int c = codes[m];
-    acc = acc + bf16_to_f32(n.w1[(m * S + c) * H + j]);
+    const int c = (int)((cw[m >> 2] >> (8 * (m & 3))) & 255u);
+    acc = acc + bf16_to_f32(w1[(m * S + c) * H]);
   }
   const float h1 = acc > 0.0f ? acc : 0.0f;
   wave_sync();
   if (lane < H) hbuf[lane] = h1;
   wave_sync();
-  acc = n.b2[j];
-  for (int i = 0; i < H; ++i) acc = fmaf(hbuf[i], bf16_to_f32(n.w2[i * H + j]), acc);
+  acc = patch_dot(hbuf, n.w2t + j * patch_ldt(H), H, n.b2[j]);
   const float h2 = acc > 0.0f ? acc : 0.0f;
   wave_sync();
   if (lane < H) hbuf[lane] = h2;
   wave_sync();
   const int k = lane < n.n_out ? lane : 0;
-  acc = n.b3[k];
-  for (int i = 0; i < H; ++i) acc = fmaf(hbuf[i], bf16_to_f32(n.w3[i * n.n_out + k]), acc);
+  acc = patch_dot(hbuf, n.w3t + k * patch_ldt(H), H, n.b3[k]);
   wave_sync();
   return lane < n.n_out ? acc : 0.0f;
 }

@@ -100,6 +100,7 @@ def test_null_handles_are_rejected_without_gpu():
         lambda: L.akmc_poisson_attach(None, None),
         lambda: L.akmc_patchnet_blob_bytes(5, 0, 8, None),
         lambda: L.akmc_patchnet_blob_bytes(5, 16, 3, None),
+        lambda: L.akmc_patchnet_blob_bytes(5, 12, 8, None),
         lambda: L.akmc_voxel_grid(None, 1, 1, 0.6, 1e-4, 0.1, None, None, None, None),
     ]
     for call in calls:
