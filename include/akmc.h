@@ -32,8 +32,10 @@
  *     u2 = ((x1 >> 11) + 1) * 2^-53.  dt = -ln(u2)/Gamma_tot.
  *   - Vacancy slots are numbered by ascending site at creation; a slot
  *     follows its vacancy.
- *   - Digest: FNV-1a 64 over the little-endian bytes of
- *     (n:int64, from_site:int32, to_site:int32) of every event.
+ *   - Digest: starting from digest0 (default the FNV-1a offset basis), every
+ *     event applies one FNV-1a step, h = (h ^ w) * 0x100000001b3 modulo
+ *     2^64, to the word w = from_site | to_site << 32 (unsigned 32-bit
+ *     sites).
  *
  * Memory: the library allocates no device memory.  The caller owns a
  * device workspace (sized by the *_workspace_bytes calls) and every device

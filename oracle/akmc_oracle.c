@@ -45,8 +45,9 @@
  *     c is the first whose running sum exceeds u1*Gamma_tot (plain
  *     left-to-right sums), falling back to the last positive rate.
  *   - dt = -ln(u2)/Gamma_tot (or 1/Gamma_tot in mean-time mode).
- *   - Event digest: FNV-1a 64 over the little-endian bytes of
- *     (n:int64, from:int32, to:int32) per event.
+ *   - Event digest: per event, one FNV-1a step (h ^= w; h *= 0x100000001b3,
+ *     modulo 2^64) on the word w = from | to << 32, starting from the FNV
+ *     offset basis.
  *
  * Precision: fp64 throughout by default.  A second mode computes energy
  * change, barrier and rate in binary32 (fmaf chain on the binary32 tables,
@@ -350,12 +351,13 @@ uint64_t orc_fnv1a(uint64_t h, const uint8_t *bytes, int64_t n) {
     return h;
 }
 
-static uint64_t digest_event(uint64_t h, int64_t n, int32_t from, int32_t to) {
-    uint8_t b[16];
-    for (int a = 0; a < 8; a++) b[a] = (uint8_t)((uint64_t)n >> (8 * a));
-    for (int a = 0; a < 4; a++) b[8 + a] = (uint8_t)((uint32_t)from >> (8 * a));
-    for (int a = 0; a < 4; a++) b[12 + a] = (uint8_t)((uint32_t)to >> (8 * a));
-    return orc_fnv1a(h, b, 16);
+/* One event of the trajectory digest: the FNV-1a step (xor, then multiply
+ * by the 64-bit FNV prime, modulo 2^64) applied once to the 64-bit word
+ * from | to << 32 (sites as unsigned 32-bit values).  For a word below 256
+ * this is FNV-1a over that one byte. */
+uint64_t orc_digest_event(uint64_t h, int32_t from, int32_t to) {
+    const uint64_t w = (uint64_t)(uint32_t)from | ((uint64_t)(uint32_t)to << 32);
+    return (h ^ w) * 0x100000001b3ULL;
 }
 
 /* -------------------------------------------------------------- selection */
@@ -465,7 +467,7 @@ static int64_t run_events(const orc_params *p, uint8_t *occ, int32_t *slots, int
         occ[i] = occ[j];
         occ[j] = (uint8_t)V;
         slots[v] = j;
-        st->digest = digest_event(st->digest, st->n, i, j);
+        st->digest = orc_digest_event(st->digest, i, j);
         st->t += dt;
         st->n += 1;
         done += 1;
@@ -562,7 +564,7 @@ void orc_follow(const orc_params *p, uint8_t *occ, int32_t *slots, int32_t nv,
                 occ[i] = occ[j];
                 occ[j] = (uint8_t)V;
                 slots[ev->slot] = j;
-                st->digest = digest_event(st->digest, st->n, i, j);
+                st->digest = orc_digest_event(st->digest, i, j);
                 st->t += dt;
             }
         }
@@ -856,7 +858,7 @@ int64_t orc_run_learned(const orc_params *p, uint8_t *occ, int32_t *slots, int32
             ev->gamma_tot = g;
             ev->dt = dt;
         }
-        st->digest = digest_event(st->digest, st->n, i, j);
+        st->digest = orc_digest_event(st->digest, i, j);
         st->t += dt;
         st->n += 1;
         done += 1;
@@ -940,7 +942,7 @@ void orc_follow_learned(const orc_params *p, uint8_t *occ, int32_t *slots, int32
                 if (fabs(dt) > scale) scale = fabs(dt);
                 double ddt = fabs(ev->dt - dt) / scale;
                 if (ddt > out[2]) out[2] = ddt;
-                st->digest = digest_event(st->digest, st->n, i, j);
+                st->digest = orc_digest_event(st->digest, i, j);
                 st->t += dt;
             }
         }

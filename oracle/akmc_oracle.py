@@ -108,6 +108,8 @@ def lib():
         L.orc_uniforms.restype = None
         L.orc_fnv1a.argtypes = [C.c_uint64, _u8p, C.c_int64]
         L.orc_fnv1a.restype = C.c_uint64
+        L.orc_digest_event.argtypes = [C.c_uint64, C.c_int32, C.c_int32]
+        L.orc_digest_event.restype = C.c_uint64
         L.orc_select.argtypes = [_f64p, C.c_int64, C.c_double, C.POINTER(C.c_double)]
         L.orc_select.restype = C.c_int64
         L.orc_gamma_tot.argtypes = [P, _u8p, _i32p, C.c_int32]
@@ -376,6 +378,11 @@ def uniforms(seed: int, stream_id: int, n: int):
 def fnv1a(data: bytes, h: int = FNV_OFFSET) -> int:
     arr = np.frombuffer(bytes(data), dtype=np.uint8).copy() if data else np.zeros(1, np.uint8)
     return lib().orc_fnv1a(h, arr, len(data))
+
+
+def digest_event(h: int, from_site: int, to_site: int) -> int:
+    """One event of the trajectory digest (orc_digest_event)."""
+    return lib().orc_digest_event(h, int(from_site), int(to_site))
 
 
 def select(rates, u1: float):

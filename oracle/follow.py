@@ -93,8 +93,7 @@ class Follower:
             self.occ[i] = self.occ[j]
             self.occ[j] = V
             self.slots[ev["slot"]] = j
-            b = (np.array([self.n], "<i8").tobytes() + np.array([i, j], "<i4").tobytes())
-            self.digest = O.fnv1a(b, self.digest)
+            self.digest = O.digest_event(self.digest, i, j)
             self.t += dt
             self.n += 1
             out["events"] += 1

@@ -91,18 +91,11 @@ __device__ __forceinline__ void event_uniforms(uint64_t seed, uint64_t stream, i
 }
 
 // -------------------------------------------------------------- digest
-// FNV-1a 64 over the 16 little-endian bytes of (n, from, to).
-__device__ __forceinline__ uint64_t fnv_event(uint64_t h, int64_t n, int32_t from, int32_t to) {
-  const uint64_t P = 0x100000001b3ull;
-  uint64_t un = (uint64_t)n;
-#pragma unroll
-  for (int a = 0; a < 8; ++a) { h ^= (un >> (8 * a)) & 0xff; h *= P; }
-  uint32_t uf = (uint32_t)from, ut = (uint32_t)to;
-#pragma unroll
-  for (int a = 0; a < 4; ++a) { h ^= (uf >> (8 * a)) & 0xff; h *= P; }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) { h ^= (ut >> (8 * a)) & 0xff; h *= P; }
-  return h;
+// One event of the trajectory digest: the FNV-1a step (xor, then multiply by
+// the 64-bit FNV prime modulo 2^64) on the word from | to << 32.
+__device__ __forceinline__ uint64_t digest_event(uint64_t h, int32_t from, int32_t to) {
+  const uint64_t w = (uint64_t)(uint32_t)from | ((uint64_t)(uint32_t)to << 32);
+  return (h ^ w) * 0x100000001b3ull;
 }
 
 // ------------------------------------------------- candidate energetics

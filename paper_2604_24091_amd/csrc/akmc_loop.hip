@@ -12,8 +12,9 @@
 //   2. selection: target = u1 * Gamma_tot, descended through a tree of
 //      binary64 partial sums held in LDS (fan-out 8 at every level: 8
 //      directions per slot, then groups of 8 slots, ...).  Every node is
-//      the left-to-right sum of its children, so the sums do not depend on
-//      G, on which slots were refreshed, or on the launch split;
+//      a fixed function of its children (a scan within its group of 8), so
+//      the sums do not depend on G, on which slots were refreshed, or on
+//      the launch split;
 //   3. dt = -ln(u2)/Gamma_tot, t += dt, digest update;
 //   4. swap of atom and vacancy in the global occupancy;
 //   5. local refresh: every slot whose vacancy lies within 4 half-lattice
@@ -1051,7 +1052,7 @@ struct Runner {
         }
       }
       if (!late_rec) t += dt;
-      dig = fnv_event(dig, n, si, sj);
+      dig = digest_event(dig, si, sj);
       n += 1;
 
       if (!MLP && na == 1) {

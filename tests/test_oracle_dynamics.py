@@ -1,5 +1,6 @@
 """Pins of the oracle's random stream, digest, selection, time and
-trajectory (orc_philox4x64_10, orc_uniforms, orc_fnv1a, orc_select, orc_run).
+trajectory (orc_philox4x64_10, orc_uniforms, orc_fnv1a, orc_digest_event,
+orc_select, orc_run).
 """
 import math
 import os
@@ -174,15 +175,29 @@ def test_frozen_state_reports(oracle_mod):
 
 
 def test_digest_definition(oracle_mod):
+    """The digest of a run is the FNV-1a step on from | to << 32 per event,
+    recomputed here with Python integers from the run's log."""
     spec = W.fe_cu_2k()
     o = oracle_mod.Oracle(spec)
     _, log = o.run(50, log=True)
     h = oracle_mod.FNV_OFFSET
     for ev in log:
-        b = (int(ev["n"]).to_bytes(8, "little") + int(ev["from_site"]).to_bytes(4, "little")
-             + int(ev["to_site"]).to_bytes(4, "little"))
-        h = oracle_mod.fnv1a(b, h)
+        w = int(ev["from_site"]) | (int(ev["to_site"]) << 32)
+        h = ((h ^ w) * 0x100000001B3) % 2**64
     assert h == o.state.digest
+
+
+def test_digest_step_is_fnv1a_on_one_byte(oracle_mod):
+    """For a word below 256 the event step is FNV-1a over that single byte
+    (the published function, pinned by its test vectors above); larger
+    words and negative sites go through the same xor-multiply."""
+    for h in (oracle_mod.FNV_OFFSET, 0, 2**64 - 1, 0x0123456789ABCDEF):
+        for b in (0, 1, 97, 255):
+            assert oracle_mod.digest_event(h, b, 0) == oracle_mod.fnv1a(bytes([b]), h)
+    h = 0x0123456789ABCDEF
+    for i, j in ((4194303, 17), (-1, 5), (5, -1), (2**31 - 1, 2**31 - 2)):
+        w = (i % 2**32) | ((j % 2**32) << 32)
+        assert oracle_mod.digest_event(h, i, j) == ((h ^ w) * 0x100000001B3) % 2**64
 
 
 def test_follow_accepts_own_log_and_rejects_a_wrong_choice(oracle_mod):
