@@ -410,6 +410,22 @@ static akmc_status run_loop(akmc_handle h, int64_t n_events, double t_end, akmc_
       return fail(AKMC_ERR_UNSUPPORTED, "the vacancies' rate tree and the attached networks exceed the "
                                         "160 KiB of LDS of a workgroup");
   }
+  // The LDS the loop leaves free in its workgroup holds the coarse vacancy
+  // grid (at most 32 KiB).
+  {
+    const size_t base = far   ? event_loop_far_lds_bytes(h->nv, h->p.precision)
+                        : lrn ? lrn_lds
+                        : mlp ? event_loop_mlp_lds_bytes(h->nv, h->p.n_species)
+                              : event_loop_lds_bytes(h->nv, 64, 1, h->p.precision);
+    const int cap = base < kLdsBytes ? (int)std::min<size_t>(kLoopGridWords, (kLdsBytes - base) / 16 * 4) : 0;
+    const int reach = far ? 6 : lrn ? 5 : 4;
+    a.grid_words = h->p.refresh == AKMC_REFRESH_FULL
+                       ? 0
+                       : vac_grid(h->p.lx, h->p.ly, h->p.lz, h->nv, reach, cap).words;
+    if (lrn)
+      lrn_lds = event_loop_lrn_lds_bytes(h->nv, h->p.precision, h->pol_blob ? h->pol_dims : nullptr,
+                                         h->pt_blob ? h->pt_dims : nullptr, a.grid_words);
+  }
   Schedule s{64, 1, 1};
   for (int64_t done = 0; done < n_events; done += kChunkEvents) {
     const int64_t n = std::min(kChunkEvents, n_events - done);
@@ -599,6 +615,7 @@ struct akmc_batch_s {
   std::vector<int> nv;
   std::vector<int64_t> nsites;
   int nv_max;
+  int grid_words;                     // LDS words of each group's vacancy grid
   LatDesc *d_descs;
   LatState *d_states;
   int32_t *d_order, *d_queue, *d_slots;
@@ -648,10 +665,11 @@ BatchLayout batch_layout(int n_rep, const akmc_params *p, const int32_t *n_vac) 
   return b;
 }
 
-// The loop keeps every group's tree, lists and boxes in LDS: a schedule is
-// usable only if (64 / lanes) * waves groups of the largest replica fit.
-bool schedule_fits(int nv_max, int group_lanes, int waves_per_block, int precision) {
-  return event_loop_lds_bytes(nv_max, group_lanes, waves_per_block, precision) <= kLdsBytes;
+// The loop keeps every group's tree, lists, boxes and vacancy grid in LDS:
+// a schedule is usable only if (64 / lanes) * waves groups of the largest
+// replica fit.
+bool schedule_fits(int nv_max, int group_lanes, int waves_per_block, int precision, int grid_words) {
+  return event_loop_lds_bytes(nv_max, group_lanes, waves_per_block, precision, grid_words) <= kLdsBytes;
 }
 
 akmc_status check_schedule(const akmc_schedule *s) {
@@ -676,6 +694,7 @@ LoopArgs batch_args(const akmc_batch_s *b, int64_t n) {
   a.queue = b->d_queue;
   a.n_lat = b->n_rep;
   a.nv_max = b->nv_max;
+  a.grid_words = b->grid_words;
   a.n_events = n;
   a.t_end = HUGE_VAL;
   a.ea_trace = b->d_trace;
@@ -775,6 +794,12 @@ akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p, const uint8_t
   b->nv.assign(nv.begin(), nv.end());
   b->nv_max = 1;
   for (int r = 0; r < n_rep; ++r) b->nv_max = std::max(b->nv_max, nv[r]);
+  // Each group's vacancy grid is sized for the largest replica (at most
+  // 2 KiB, so that small groups still pack several to a workgroup).
+  b->grid_words = 0;
+  if (!b->refresh_full)
+    for (int r = 0; r < n_rep; ++r)
+      b->grid_words = std::max(b->grid_words, vac_grid(p[r].lx, p[r].ly, p[r].lz, nv[r], 4, kBatchGridWords).words);
   b->d_descs = (LatDesc *)(b->ws + lay.descs);
   b->d_states = (LatState *)(b->ws + lay.states);
   b->d_order = (int32_t *)(b->ws + lay.order);
@@ -787,7 +812,7 @@ akmc_status akmc_batch_create(int32_t n_rep, const akmc_params *p, const uint8_t
   // 8 lanes per replica, or the fewest lanes whose groups fit in LDS (64
   // lanes always fit: one group per wavefront).
   int g0 = 8;
-  while (g0 < 64 && !schedule_fits(b->nv_max, g0, 1, b->precision)) g0 *= 2;
+  while (g0 < 64 && !schedule_fits(b->nv_max, g0, 1, b->precision, b->grid_words)) g0 *= 2;
   b->sched = akmc_schedule{g0, 1, 0, 0, 1 << 30};
 
   std::vector<LatState> states(n_rep);
@@ -840,7 +865,7 @@ akmc_status akmc_batch_set_schedule(akmc_batch b, const akmc_schedule *s) {
   if (!b) return fail(AKMC_ERR_INVALID, "batch is NULL");
   akmc_status st = check_schedule(s);
   if (st != AKMC_OK) return st;
-  if (!schedule_fits(b->nv_max, s->group_lanes, s->waves_per_block, b->precision))
+  if (!schedule_fits(b->nv_max, s->group_lanes, s->waves_per_block, b->precision, b->grid_words))
     return fail(AKMC_ERR_UNSUPPORTED,
                 "schedule needs more than the 160 KiB of LDS of a workgroup: use more lanes per "
                 "replica or fewer waves per block");
@@ -875,7 +900,7 @@ akmc_status akmc_batch_autotune(akmc_batch b, int64_t trial_events, akmc_schedul
   float best_ms = 1e30f;
   for (int G : lanes)
     for (int W : waves) {
-      if (!schedule_fits(b->nv_max, G, W, b->precision)) continue;
+      if (!schedule_fits(b->nv_max, G, W, b->precision, b->grid_words)) continue;
       akmc_schedule s = keep;
       s.group_lanes = G;
       s.waves_per_block = W;

@@ -96,6 +96,9 @@ struct LoopArgs {
   // by inv_tau, Poisson time network (NULL: time_mode).
   const unsigned char *pol_blob, *pt_blob;
   float inv_tau;
+  // LDS words of each group's coarse vacancy grid (0: none); every lattice
+  // of the launch takes vac_grid(its edges, its slots, reach, grid_words).
+  int32_t grid_words;
 };
 
 // LDS carve-up of one lattice group in the event loop.  Every array is
@@ -112,13 +115,56 @@ struct GroupLayout {
   int qlen[kMaxLevels + 1];       // elements of level l (1-based)
   int qoff[kMaxLevels + 1];       // element offset of level l in the Q region
   int off_part, off_q, off_pos, off_aff, off_la, off_lb, off_spec, off_box, off_tab, off_rng, off_tmp;
+  int off_grid, grid_words;
   int bytes;
 };
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-// far: the pair model out to 6.0 A (11x11x11 boxes, tables of 6 shells).
-__host__ __device__ inline GroupLayout make_layout(int nv_max, int G, int fp32, int far = 0) {
+// Coarse grid of vacancy counts of one lattice, used to rule out other
+// vacancies near a jump without scanning every slot.  Cells are 2^lc
+// half-lattice units per axis (the last cell of an axis also takes the
+// remainder of the edge), so every cell spans at least 2^lc units; counts
+// sit in fields of 2^fb bits (wide enough for nv) packed into 32-bit words.
+// With 2^lc >= 2R a window of 2R + 1 units along an axis touches at most
+// two cells, the cells of its two ends: the 8 cells of (X +- R, Y +- R,
+// Z +- R) hold every vacancy within Chebyshev distance R of (X, Y, Z).
+// Cells grow by powers of two until the grid fits cap_words (words = 0:
+// no grid fits).
+struct VacGrid {
+  int lc, fb, nx, ny, nz, words;
+};
+
+__host__ __device__ inline VacGrid vac_grid(int lx, int ly, int lz, int nv, int reach, int cap_words) {
+  VacGrid g;
+  g.lc = 1;
+  while ((1 << g.lc) < 2 * reach) ++g.lc;
+  g.fb = nv <= 15 ? 2 : (nv <= 255 ? 3 : 4);
+  for (;;) {
+    g.nx = (2 * lx) >> g.lc;
+    g.ny = (2 * ly) >> g.lc;
+    g.nz = (2 * lz) >> g.lc;
+    g.nx = g.nx < 1 ? 1 : g.nx;
+    g.ny = g.ny < 1 ? 1 : g.ny;
+    g.nz = g.nz < 1 ? 1 : g.nz;
+    const long long cells = (long long)g.nx * g.ny * g.nz;
+    const long long words = ((cells << g.fb) + 31) >> 5;
+    if (words <= cap_words) {
+      g.words = (int)words;
+      return g;
+    }
+    if (cells == 1) {
+      g.words = 0;
+      return g;
+    }
+    ++g.lc;
+  }
+}
+
+// far: the pair model out to 6.0 A (11x11x11 boxes, tables of 6 shells);
+// grid_words: LDS words of the vacancy grid.
+__host__ __device__ inline GroupLayout make_layout(int nv_max, int G, int fp32, int far = 0,
+                                                   int grid_words = 0) {
   GroupLayout L{};
   L.nv_max = nv_max;
   L.G = G;
@@ -146,6 +192,8 @@ __host__ __device__ inline GroupLayout make_layout(int nv_max, int G, int fp32, 
   L.off_tab = o;  o = align16(o + (64 + 64 + 8 + (far ? 4 * 64 : 0)) * real);
   L.off_rng = o;  o = align16(o + 2 * G * 8);
   L.off_tmp = o;  o = align16(o + G * 8);
+  L.off_grid = o; o = align16(o + grid_words * 4);
+  L.grid_words = grid_words;
   L.bytes = o;
   return L;
 }
@@ -162,16 +210,17 @@ hipError_t launch_event_loop(const LoopArgs &a, int precision, int refresh_full,
 // Event loop with the learned barrier (one 64-lane group, binary32 rates).
 hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_species,
                                  hipStream_t stream);
-size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision);
+size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision,
+                            int grid_words = 0);
 // Event loop with the learned runtime forms (one 64-lane group); lds from
 // event_loop_lrn_lds_bytes with each attached network's (S, H, n_out).
 // Event loop of the pair model out to 6.0 A (one 64-lane group).
 hipError_t launch_event_loop_far(const LoopArgs &a, int precision, int refresh_full, hipStream_t stream);
-size_t event_loop_far_lds_bytes(int nv_max, int precision);
+size_t event_loop_far_lds_bytes(int nv_max, int precision, int grid_words = 0);
 hipError_t launch_event_loop_lrn(const LoopArgs &a, int precision, int refresh_full, size_t lds,
                                  hipStream_t stream);
 size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3],
-                                const int pt_dims[3]);
+                                const int pt_dims[3], int grid_words = 0);
 // Local patch networks on listed sites: out[n][n_out] (NaN for a site
 // outside the lattice).
 hipError_t launch_patch_eval(const LatDesc *d_desc, const uint8_t *d_occ, const unsigned char *d_blob,
@@ -186,9 +235,12 @@ hipError_t launch_priority(const LatDesc *d_descs, const void *d_trace, int fp32
                            double *d_w, int32_t *d_order, hipStream_t st);
 hipError_t launch_order_index(int32_t *d_order, int n_rep, hipStream_t st);
 // LDS of the event loop with the learned barrier (one 64-lane group).
-size_t event_loop_mlp_lds_bytes(int nv_max, int n_species);
+size_t event_loop_mlp_lds_bytes(int nv_max, int n_species, int grid_words = 0);
 // LDS a workgroup may hold on gfx950.
 constexpr size_t kLdsBytes = 160 * 1024;
+// Largest vacancy grid of a single-lattice loop and of a batch group (words).
+constexpr int kLoopGridWords = 8192;
+constexpr int kBatchGridWords = 512;
 hipError_t launch_queue_reset(int32_t *queue, hipStream_t stream);
 hipError_t launch_cluster_hist(const uint8_t *d_occ, int lx, int ly, int lz, int species,
                                int64_t max_size, int64_t *d_hist, int *d_parent, int *d_size,

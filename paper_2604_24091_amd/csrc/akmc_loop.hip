@@ -216,6 +216,8 @@ struct Lds {
   Real *Dx;         // shells 3..6 of the pair model out to 6.0 A (4 rows of 64)
   double *ru1, *rw; // uniforms u1 and -ln u2 of the next G events
   double *tmp;      // G values exchanged between the lanes of a group
+  uint32_t *grid;   // coarse vacancy counts (vac_grid), grid_words words
+  int grid_words;
 };
 
 template <class Real>
@@ -236,6 +238,8 @@ __device__ __forceinline__ Lds<Real> carve(unsigned char *base, const GroupLayou
   s.ru1 = (double *)(base + L.off_rng);
   s.rw = s.ru1 + L.G;
   s.tmp = (double *)(base + L.off_tmp);
+  s.grid = (uint32_t *)(base + L.off_grid);
+  s.grid_words = L.grid_words;
   return s;
 }
 
@@ -787,6 +791,25 @@ struct Runner {
     return lane_value(acc, 63);
   }
 
+  // Coarse vacancy grid (vac_grid): the cell of a position, and the count
+  // field of a cell; the moved vacancy's count goes from cell to cell by
+  // LDS atomics (no borrow: a count is at least 1 where it is decremented).
+  __device__ __forceinline__ static int grid_cell(const VacGrid &vg, int X, int Y, int Z) {
+    const int cx = min(X >> vg.lc, vg.nx - 1), cy = min(Y >> vg.lc, vg.ny - 1),
+              cz = min(Z >> vg.lc, vg.nz - 1);
+    return (cz * vg.ny + cy) * vg.nx + cx;
+  }
+  __device__ __forceinline__ int grid_count(const VacGrid &vg, int cell) const {
+    const uint32_t w = s.grid[cell >> (5 - vg.fb)];
+    return (int)((w >> ((cell << vg.fb) & 31)) & ((1u << (1 << vg.fb)) - 1u));
+  }
+  __device__ __forceinline__ void grid_inc(const VacGrid &vg, int cell) {
+    atomicAdd(&s.grid[cell >> (5 - vg.fb)], 1u << ((cell << vg.fb) & 31));
+  }
+  __device__ __forceinline__ void grid_dec(const VacGrid &vg, int cell) {
+    atomicSub(&s.grid[cell >> (5 - vg.fb)], 1u << ((cell << vg.fb) & 31));
+  }
+
   __device__ void run(int lat) {
     const LatDesc *d = a.descs + lat;
     LatState *st = a.states + lat;
@@ -823,11 +846,20 @@ struct Runner {
     if (frozen) return;
     const int64_t clk0 = wall_clock64();
 
+    // The vacancy grid rules out other slots near a jump in one LDS read
+    // per lane; it only decides whether the exact scan runs.
+    const VacGrid vg = vac_grid(g.lx, g.ly, g.lz, nv, REACH, s.grid_words);
+    const bool use_grid = !full && vg.words > 0;
+    if (use_grid) {
+      for (int w = gl; w < vg.words; w += G) s.grid[w] = 0u;
+      gsync();
+    }
     for (int v = gl; v < nv; v += G) {
       int X, Y, Z;
       pos_of(g, slots[v], X, Y, Z);
       s.pos[v] = pack_pos(X, Y, Z);
       s.aff[v] = v;
+      if (use_grid) grid_inc(vg, grid_cell(vg, X, Y, Z));
     }
     gsync();
     akmc_event none{};
@@ -1021,8 +1053,29 @@ struct Runner {
             hit[u] = b0 + u * G + gl < nv && max(dx, max(dy, dz)) <= REACH;
           }
         };
+        // The grid first: lane b < 8 reads the cell of (X +- R, Y +- R,
+        // Z +- R) (bit 0, 1, 2 of b: + in x, y, z) and counts it without
+        // the moved vacancy, still at i there; only if some vacancy may be
+        // that close do all slots take the exact test.
+        bool scan = true;
+        if (use_grid) {
+          const int ci = grid_cell(vg, X, Y, Z);
+          int c = 0;
+          if (gl < 8) {
+            const int cell = grid_cell(vg, wrapc(X + ((gl & 1) ? REACH : -REACH), g.X2),
+                                       wrapc(Y + ((gl & 2) ? REACH : -REACH), g.Y2),
+                                       wrapc(Z + ((gl & 4) ? REACH : -REACH), g.Z2));
+            c = grid_count(vg, cell) - (cell == ci ? 1 : 0);
+          }
+          scan = gp.ballot(c > 0) != 0;
+          const int cj = grid_cell(vg, JX, JY, JZ);
+          if (gl == 0 && cj != ci) {
+            grid_dec(vg, ci);
+            grid_inc(vg, cj);
+          }
+        }
         bool others = false;
-        for (int b0 = 0; b0 < nv; b0 += 4 * G) {
+        for (int b0 = 0; scan && b0 < nv; b0 += 4 * G) {
           bool hit[4];
           hits(b0, hit);
           bool oth = false;
@@ -1188,18 +1241,19 @@ hipError_t launch_queue_reset(int32_t *queue, hipStream_t stream) {
   return hipGetLastError();
 }
 
-size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision) {
-  const GroupLayout L = make_layout(nv_max, group_lanes, precision == AKMC_FP32);
+size_t event_loop_lds_bytes(int nv_max, int group_lanes, int waves_per_block, int precision,
+                            int grid_words) {
+  const GroupLayout L = make_layout(nv_max, group_lanes, precision == AKMC_FP32, 0, grid_words);
   return (size_t)L.bytes * (size_t)(64 / group_lanes) * (size_t)waves_per_block;
 }
 
-size_t event_loop_mlp_lds_bytes(int nv_max, int n_species) {
-  return (size_t)make_layout(nv_max, 64, 1).bytes + mlp_loop_lds_bytes(n_species);
+size_t event_loop_mlp_lds_bytes(int nv_max, int n_species, int grid_words) {
+  return (size_t)make_layout(nv_max, 64, 1, 0, grid_words).bytes + mlp_loop_lds_bytes(n_species);
 }
 
 template <int G, int W, bool FP32>
 static hipError_t launch_one(const LoopArgs &a, const Schedule &s, hipStream_t stream) {
-  const GroupLayout L = make_layout(a.nv_max, G, FP32 ? 1 : 0);
+  const GroupLayout L = make_layout(a.nv_max, G, FP32 ? 1 : 0, 0, a.grid_words);
   const size_t lds = (size_t)L.bytes * (64 / G) * W;
   // Lattices of at most 64 slots need two tree levels: a shorter unrolled
   // descent and re-sum.
@@ -1243,8 +1297,8 @@ hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_spec
   b.refresh_full = refresh_full;
   hipError_t e = launch_queue_reset(a.queue, stream);
   if (e != hipSuccess) return e;
-  const GroupLayout L = make_layout(a.nv_max, 64, 1);
-  const size_t lds = event_loop_mlp_lds_bytes(a.nv_max, n_species);
+  const GroupLayout L = make_layout(a.nv_max, 64, 1, 0, a.grid_words);
+  const size_t lds = event_loop_mlp_lds_bytes(a.nv_max, n_species, a.grid_words);
   auto kern = k_event_loop<64, 1, true, true>;
   e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -1252,13 +1306,13 @@ hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_spec
   return hipGetLastError();
 }
 
-size_t event_loop_far_lds_bytes(int nv_max, int precision) {
-  return (size_t)make_layout(nv_max, 64, precision == AKMC_FP32, 1).bytes;
+size_t event_loop_far_lds_bytes(int nv_max, int precision, int grid_words) {
+  return (size_t)make_layout(nv_max, 64, precision == AKMC_FP32, 1, grid_words).bytes;
 }
 
 template <bool FP32>
 static hipError_t launch_far(const LoopArgs &a, hipStream_t stream) {
-  const GroupLayout L = make_layout(a.nv_max, 64, FP32 ? 1 : 0, 1);
+  const GroupLayout L = make_layout(a.nv_max, 64, FP32 ? 1 : 0, 1, a.grid_words);
   auto kern = L.nlev_max <= 2 ? k_event_loop<64, 1, FP32, false, 2, false, true>
                               : k_event_loop<64, 1, FP32, false, 3, false, true>;
   const size_t lds = (size_t)L.bytes;
@@ -1279,8 +1333,8 @@ hipError_t launch_event_loop_far(const LoopArgs &a, int precision, int refresh_f
 }
 
 size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3],
-                                const int pt_dims[3]) {
-  const GroupLayout L = make_layout(nv_max, 64, precision == AKMC_FP32);
+                                const int pt_dims[3], int grid_words) {
+  const GroupLayout L = make_layout(nv_max, 64, precision == AKMC_FP32, 0, grid_words);
   size_t b = (size_t)L.bytes + 16 * (size_t)nv_max + 8 * 64 + 4 * 64 + kObsN * 8;
   if (pol_dims) b += (size_t)patch_lds_bytes(pol_dims[0], pol_dims[1], pol_dims[2]);
   if (pt_dims) b += (size_t)patch_lds_bytes(pt_dims[0], pt_dims[1], pt_dims[2]);
@@ -1289,7 +1343,7 @@ size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3]
 
 template <bool FP32>
 static hipError_t launch_lrn(const LoopArgs &a, size_t lds, hipStream_t stream) {
-  const GroupLayout L = make_layout(a.nv_max, 64, FP32 ? 1 : 0);
+  const GroupLayout L = make_layout(a.nv_max, 64, FP32 ? 1 : 0, 0, a.grid_words);
   auto kern = L.nlev_max <= 2 ? k_event_loop<64, 1, FP32, false, 2, true>
                               : k_event_loop<64, 1, FP32, false, 3, true>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -131,6 +131,47 @@ def test_local_refresh_equals_full_refresh():
     assert np.array_equal(a[3], b[3])
 
 
+def _clustered(rng, dims, S, nv, half):
+    """A lattice whose nv vacancies all lie within `half` cells of the
+    origin (periodic), so jumps often have other vacancies close by and the
+    cluster straddles the faces of the box."""
+    spec = W.random_lattice(rng, dims, S, 0, solute_total=0.2)
+    lx, ly, lz = dims
+    occ = spec.occ.copy()
+    cand = []
+    for b in (0, 1):
+        for z in range(-half, half + 1):
+            for y in range(-half, half + 1):
+                for x in range(-half, half + 1):
+                    cand.append(b * lx * ly * lz + ((z % lz) * ly + (y % ly)) * lx + (x % lx))
+    occ[rng.choice(np.array(cand), size=nv, replace=False)] = S - 1
+    return W.LatticeSpec(**{**spec.__dict__, "occ": occ})
+
+
+@pytest.mark.parametrize("dims,nv,half,n", [((13, 11, 18), 120, 99, 6000), ((26, 22, 17), 60, 3, 6000),
+                                            ((40, 40, 40), 200, 5, 4000)])
+def test_vacancy_grid_local_equals_full_and_oracle(oracle_mod, dims, nv, half, n):
+    """Lattices whose coarse vacancy grid has several cells per axis (edges
+    not multiples of the cell, so the last cell of an axis is wider), with
+    vacancies spread out or packed around a corner of the periodic box:
+    LOCAL refresh (the grid decides when the exact scan runs) equals FULL
+    refresh bit for bit, chunked runs equal one run, and the binary64
+    trajectory equals the oracle's."""
+    rng = np.random.default_rng(sum(dims) + nv)
+    if half >= max(dims):
+        spec = W.random_lattice(rng, dims, 5, nv, solute_total=0.2)
+    else:
+        spec = _clustered(rng, dims, 5, nv, half)
+    banner("vacancy grid dims=%s nv=%d half=%d" % (dims, nv, half))
+    a = run_gpu(spec, n, refresh=akmc.REFRESH_LOCAL)
+    b = run_gpu(spec, n, refresh=akmc.REFRESH_FULL)
+    c = run_gpu(spec, n, refresh=akmc.REFRESH_LOCAL, chunks=[1, 99, n - 100])
+    for x in (b, c):
+        assert np.array_equal(a[0], x[0]) and a[2].digest == x[2].digest and a[2].t == x[2].t
+        assert np.array_equal(a[3], x[3])
+    assert_matches_oracle(oracle_mod, spec, a, n)
+
+
 def test_chunked_steps_equal_one_step():
     banner("loop chunking")
     spec = W.random_lattice(np.random.default_rng(22), (8, 8, 8), 5, 20, solute_total=0.2)
