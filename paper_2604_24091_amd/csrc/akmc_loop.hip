@@ -355,6 +355,11 @@ struct Runner {
   // moving species seen in training.
   uint32_t oodw[4], seen;
   double top_q;   // lane c < 8: partial c of the top tree level (cached between events)
+  // 64-lane groups keep tree levels 2 and 3 in registers as well: lane j
+  // holds node j's value (the total of its child group; t2, t3) and its
+  // inclusive partial (q2, q3), zero beyond the level's length.  The LDS
+  // copy stays current for the general refresh path.
+  double t2, q2, t3, q3;
   Real *eat;      // barrier trace of this lattice (LoopArgs::ea_trace) or NULL
   // learned runtime forms
   bool has_pol, has_pt;
@@ -762,7 +767,66 @@ struct Runner {
 
   __device__ double gamma_tot() {
     top_q = gp.gl < nl(nlev) ? Q(nlev)[gp.gl] : 0.0;
+    if (G == 64 && nlev >= 2) {
+      const bool in2 = gp.gl < nl(2);
+      t2 = in2 ? node_value(2, gp.gl) : 0.0;
+      q2 = in2 ? Q(2)[gp.gl] : 0.0;
+      const bool in3 = nlev >= 3 && gp.gl < nl(3);
+      t3 = in3 ? node_value(3, gp.gl) : 0.0;
+      q3 = in3 ? Q(3)[gp.gl] : 0.0;
+    }
     return Q(nlev)[nl(nlev) - 1];
+  }
+
+  // update_path for a 64-lane group with at least two levels: x1 (lane
+  // c < 8) holds the totals of the 8 slots of v's level-1 group, read
+  // before this event changed anything; levels 2 and 3 come from the
+  // registers.  The same partials as update_path, the same LDS stores.
+  __device__ double update_path_regs(int v, double gv, double x1) {
+    const int gl = gp.gl, c = gl & 7;
+    const int g1 = v >> 3, g2 = v >> 6;
+    x1 = c == (v & 7) ? gv : x1;
+    const double p1 = subgroup_prefix(x1, c);
+    const int cnt1 = min(8, nv - 8 * g1);
+    if (gl < cnt1) Q(1)[8 * g1 + gl] = p1;
+    double fresh = lane_value(p1, cnt1 - 1);
+    t2 = gl == g1 ? fresh : t2;
+    q2 = subgroup_prefix(t2, c);
+    const int cnt2 = min(8, nl(2) - 8 * g2);
+    if ((gl >> 3) == g2 && c < cnt2) Q(2)[gl] = q2;
+    fresh = lane_value(q2, 8 * g2 + cnt2 - 1);
+    if (nlev == 2) {
+      top_q = gl < 8 ? q2 : 0.0;
+    } else {
+      t3 = gl == g2 ? fresh : t3;
+      q3 = subgroup_prefix(t3, c);
+      const int cnt3 = nl(3);
+      if (gl < cnt3) Q(3)[gl] = q3;
+      top_q = gl < 8 ? q3 : 0.0;
+      fresh = lane_value(q3, cnt3 - 1);
+    }
+    gsync();
+    return fresh;
+  }
+
+  // One selection step at level l >= 2 from the registers (a 64-lane
+  // group): the children of the node whose first child is `base` sit in
+  // lanes base .. base+cnt-1 of q (partials) and t (values).  The same
+  // comparisons and fallback as the LDS step of the descent.
+  __device__ __forceinline__ int select_regs(int l, int base, double q, double t, double &tgt) const {
+    const int gl = gp.gl;
+    const int cnt = min(8, nl(l) - base);
+    const bool in = gl >= base && gl < base + cnt;
+    uint64_t m = (gp.ballot(in && q > tgt) >> base) & 0xffull;
+    int c;
+    if (m) {
+      c = __ffsll((unsigned long long)m) - 1;
+    } else {
+      const uint64_t m2 = (gp.ballot(in && t > 0.0) >> base) & 0xffull;
+      c = m2 ? 63 - __clzll((long long)m2) : 0;
+    }
+    if (c > 0) tgt = tgt - lane_value(q, base + c - 1);
+    return base + c;
   }
 
   // x of lane 15 of the previous 16-lane row (DPP row_bcast:15; rows in
@@ -908,9 +972,17 @@ struct Runner {
       // offsets are constants and the descent stays in scalar registers.
       int node = 0;
       bool skip = false;
+      // A 64-lane group takes levels nlev .. 2 from the registers, then
+      // levels 1 and 0 in one LDS round trip.
+      int ltop = nlev;
+      if (G == 64 && nlev >= 2) {
+        if (nlev == 3) node = select_regs(3, 0, q3, t3, tgt);
+        node = select_regs(2, nlev == 3 ? 8 * node : 0, q2, t2, tgt);
+        ltop = 1;
+      }
 #pragma unroll
       for (int l = KL; l >= 0; --l) {
-        if (l > nlev) continue;
+        if (l > ltop) continue;
         if (skip) {
           skip = false;
           continue;
@@ -972,6 +1044,13 @@ struct Runner {
         node = base + c;
       }
       const int v = node >> 3, k = node & 7;
+      // Totals of the 8 slots of v's level-1 group, for the tree update at
+      // the end of the event (read together with the chosen candidate).
+      double x1 = 0.0;
+      if (G == 64 && nlev >= 2) {
+        const int u = 8 * (v >> 3) + (gl & 7);
+        x1 = gl < 8 && u < nv ? s.part[u * 8 + 7] : 0.0;
+      }
       int A = s.spec[v * 8 + k];
       int pp = s.pos[v];
       if (G == 64) {  // one lattice per wavefront: keep the event's scalars in SGPRs
@@ -1136,7 +1215,8 @@ struct Runner {
         if (LRN) r = learned_pass(1, 0, gl >> 3, kk, r, v);
         const double pfx = subgroup_prefix(r, kk);
         if (gl < 8) s.part[v * 8 + kk] = pfx;
-        gtot = update_path(v, lane_value(pfx, 7));
+        gtot = G == 64 && nlev >= 2 ? update_path_regs(v, lane_value(pfx, 7), x1)
+                                    : update_path(v, lane_value(pfx, 7));
       } else {
         refresh(na, si, sj, A, false, nullptr, rec);
         update_tree(na);
