@@ -1002,6 +1002,9 @@ struct Runner {
           const bool inB = inA && c2 < min(8, nlB - baseB);
           const int ib = min(baseB + c2, nlB - 1);
           const double qb = l >= 2 ? Q(l - 1)[ib] : s.part[ib];
+          // all three reads in one round trip: keeps the compiler from
+          // moving the last two behind the first comparison
+          __asm__ volatile("" ::"v"(qa), "v"(qp), "v"(qb));
           const uint64_t mA = gp.ballot(c2 == 0 && inA && qa > tgt);
           if (mA) {
             const int cs = (__ffsll((unsigned long long)mA) - 1) >> 3;
@@ -1056,6 +1059,8 @@ struct Runner {
       if (G == 64) {  // one lattice per wavefront: keep the event's scalars in SGPRs
         A = __builtin_amdgcn_readfirstlane(A);
         pp = __builtin_amdgcn_readfirstlane(pp);
+        // x1 arrives with A and pp (not re-read at its use)
+        __asm__ volatile("" ::"v"(x1));
       }
       const int X = pos_x(pp), Y = pos_y(pp), Z = pos_z(pp);
       const int JX = wrapc(X + dir_sx(k), g.X2), JY = wrapc(Y + dir_sy(k), g.Y2),
@@ -1309,8 +1314,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayo
     int idx = 0;
     if (gp.gl == 0) idx = atomicAdd(a.queue, 1);
     idx = gp.bcast(idx, 0);
+    // one lattice per wavefront: its index, and everything derived from
+    // it, is uniform (scalar registers and branches)
+    if (G == 64) idx = __builtin_amdgcn_readfirstlane(idx);
     if (idx >= a.n_lat) break;
-    run.run(a.order[idx]);
+    int lat = a.order[idx];
+    if (G == 64) lat = __builtin_amdgcn_readfirstlane(lat);
+    run.run(lat);
   }
 }
 
