@@ -1224,8 +1224,21 @@ struct Runner {
                                     : update_path(v, lane_value(pfx, 7));
       } else {
         refresh(na, si, sj, A, false, nullptr, rec);
-        update_tree(na);
-        gtot = gamma_tot();
+        if (G == 64 && nlev >= 2 && na <= 8) {
+          // A few refreshed slots: their tree paths one after the other
+          // (each re-sums its groups from the current totals, so the last
+          // update leaves every changed node equal to the level-by-level
+          // fold).
+          for (int p = 0; p < na; ++p) {
+            const int u = __builtin_amdgcn_readfirstlane(s.aff[p]);
+            const int ug = 8 * (u >> 3) + (gl & 7);
+            const double xu = gl < 8 && ug < nv ? s.part[ug * 8 + 7] : 0.0;
+            gtot = update_path_regs(u, lane_value(xu, u & 7), xu);
+          }
+        } else {
+          update_tree(na);
+          gtot = gamma_tot();
+        }
       }
       if (LRN) {
         const double g_prev = gphys, u_prev = uval;
