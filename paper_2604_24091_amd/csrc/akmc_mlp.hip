@@ -6,11 +6,12 @@
 // fused layers, and trains with AdamW at batch 256 (Sec. IV-C).  Here every
 // wavefront owns 16 candidates (one 16-row tile of the bf16 16x16x32 MFMA);
 // both layers and the activation run in one kernel with the weights staged
-// in LDS.  Training splits a batch over wavefronts: each computes the
-// gradient of its 16 rows (the weight gradients use the 16x16x16 MFMA with
-// the 16 rows as the reduction dimension, reading the activations straight
-// from the accumulator layout), and one update kernel sums the partial
-// gradients in a fixed order and applies AdamW.
+// in LDS.  Training gives every 16 rows of a batch a block of 8
+// wavefronts, one per 16 hidden units: each computes its tile of both
+// layers and of the gradients (the weight gradients on the 16x16x16 MFMA
+// with the 16 rows as the reduction dimension), the activation tiles pass
+// through LDS, and one update kernel sums the blocks' partial gradients in
+// a fixed order and applies AdamW.
 #include <hip/hip_runtime.h>
 
 #include "akmc_device.hpp"
@@ -135,11 +136,6 @@ __global__ __launch_bounds__(256) void k_ood_fit(const uint8_t *__restrict__ env
 
 // ------------------------------------------------------ bulk inference
 
-// Per training wavefront: 16 rows of 32 codes, then one area for the
-// one-hot input tile and, once layer 1 has read it, the 16-row activation
-// tile (one wavefront's LDS operations take effect in program order).
-constexpr int kWaveBytes = 512 + kTileBytes;
-
 // Bulk inference: a block of up to kFwdWavesMax wavefronts shares the
 // weights staged in LDS; each wavefront owns one tile area sized for the
 // species count (fwd_wave_bytes), holding the one-hot input tile and, once
@@ -189,8 +185,6 @@ __global__ __launch_bounds__(64 * kFwdWavesMax) void k_mlp_forward(const unsigne
 
 // ------------------------------------------------------------ training
 
-constexpr int kTrainWaves = 4;
-
 // Dataset row of batch position b: a keyed bijection of [0, n) (four-round
 // Feistel network on the next power of two with cycle walking), a fresh
 // permutation per epoch.
@@ -215,6 +209,21 @@ __device__ __forceinline__ int64_t permute_row(int64_t b, int64_t n, uint64_t ke
   return (int64_t)x;
 }
 
+// Partial gradients of one wavefront: nparams + 1 floats (the last is the
+// loss partial), padded to a multiple of 4.  The weight matrices W1 and W2
+// are stored in the order of the 16x16 MFMA accumulator tiles that produce
+// them (tile by tile, lane by lane, the lane's 4 rows), so that each tile
+// is one 16-byte store per lane; part_index maps a parameter index there.
+__host__ __device__ inline int part_stride(int np) { return (np + 1 + 3) & ~3; }
+__host__ __device__ inline int tile_pos(int row, int col) {
+  return (((row >> 4) * (kHid / 16) + (col >> 4)) * 64 + ((row & 15) >> 2) * 16 + (col & 15)) * 4 + (row & 3);
+}
+__host__ __device__ inline int part_index(const MlpLayout &L, int p) {
+  if (p < L.ob1) return L.oW1 + tile_pos(p / kHid, p % kHid);
+  if (p >= L.oW2 && p < L.ob2) return L.oW2 + tile_pos((p - L.oW2) / kHid, (p - L.oW2) % kHid);
+  return p;
+}
+
 struct TrainArgs {
   const unsigned char *blob;
   const uint8_t *env;
@@ -225,153 +234,225 @@ struct TrainArgs {
   int64_t start;        // first batch position of this step in the epoch order
   uint64_t perm_key;    // 0: identity order
   int32_t perm_bits;
-  float *partial;       // [n_waves][nparams + 1] (last: loss partial)
+  float *partial;       // [n_waves][part_stride(nparams)] (part_index order)
 };
 
-__global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_partial(TrainArgs ta) {
+// One block of kTrainTileWaves wavefronts per 16 rows of the batch;
+// wavefront w owns hidden units 16w .. 16w+15 of both layers, so each
+// layer is one 16x16 matrix-core tile per wavefront, with the activation
+// tiles exchanged in LDS.  The partial gradients of the 16 rows are the
+// same numbers the whole-network-per-wavefront form gave: every tile and
+// every reduction has the same operands in the same order (the output y is
+// summed over the 8 tiles in tile order by every wavefront).
+constexpr int kTrainTileWaves = kHid / 16;
+
+__global__ __launch_bounds__(64 * kTrainTileWaves) void k_mlp_train_partial(TrainArgs ta) {
   extern __shared__ __align__(16) unsigned char mlp_lds[];
   const MlpHeader *hdr = (const MlpHeader *)ta.blob;
   const int S = hdr->S, k1 = hdr->k1, np = hdr->nparams;
   const MlpLayout L = mlp_layout(S);
-  unsigned short *w1t = (unsigned short *)mlp_lds;
-  unsigned short *w2t = w1t + kHid * mlp_ld1(k1);
-  unsigned short *w2r = w2t + kHid * kLdH;
-  unsigned char *per_wave = (unsigned char *)(w2r + kHid * kLdH);
-  stage_rows8(w1t, (const unsigned short *)(ta.blob + L.w1t), kHid, k1, mlp_ld1(k1), threadIdx.x, blockDim.x);
-  stage_rows8(w2t, (const unsigned short *)(ta.blob + L.w2t), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
-  stage_rows8(w2r, (const unsigned short *)(ta.blob + L.w2r), kHid, kHid, kLdH, threadIdx.x, blockDim.x);
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int ld1 = mlp_ld1(k1);
+  unsigned short *atile = (unsigned short *)mlp_lds;          // one-hot inputs [16][ld1]
+  unsigned short *h1s = atile + 16 * ld1;                       // h1 [16][kLdH]
+  unsigned short *h2s = h1s + 16 * kLdH;                        // h2 [16][kLdH]
+  unsigned short *dzs = h2s + 16 * kLdH;                        // dz2 [16][kLdH]
+  uint8_t *senv = (uint8_t *)(dzs + 16 * kLdH);                 // codes [16][32]
+  const unsigned short *gw1t = (const unsigned short *)(ta.blob + L.w1t);  // [128][k1]
+  const unsigned short *gw2t = (const unsigned short *)(ta.blob + L.w2t);  // [o][i]
+  const unsigned short *gw2r = (const unsigned short *)(ta.blob + L.w2r);  // [i][o]
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int r = l & 15, q = l >> 4;
-  uint8_t *senv = per_wave + wave * kWaveBytes;
-  unsigned short *hst = (unsigned short *)(senv + 512);
-  unsigned short *atile = hst;
+  const int col = 16 * w + r;  // this lane's hidden unit
   const float *prm = (const float *)(ta.blob + L.params);
   const float mu = hdr->mu, sigma = hdr->sigma;
-  const int gw = blockIdx.x * kTrainWaves + wave;  // wavefront index within the batch
-  const int row0 = gw * 16;
-  __shared__ float s_t[kTrainWaves][16];
-  __shared__ int s_valid[kTrainWaves][16];
-  if (l < 16) {
-    const int b = row0 + l;
-    float t = 0.f;
-    int valid = 0;
-    int64_t row = -1;
+  const int row0 = blockIdx.x * 16;
+  // This lane's weight operands of all three products, read before the
+  // batch rows so that their latency overlaps the setup.
+  constexpr int kMaxT1 = mlp_k1(8) / 32;
+  const int nk = k1 / 32;
+  bf16x8 bw1[kMaxT1], bw2[4], bw2r[4];
+#pragma unroll
+  for (int t = 0; t < kMaxT1; ++t)
+    if (t < nk) bw1[t] = *(const bf16x8 *)(gw1t + col * k1 + 32 * t + 8 * q);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    bw2[t] = *(const bf16x8 *)(gw2t + col * kHid + 32 * t + 8 * q);
+    bw2r[t] = *(const bf16x8 *)(gw2r + col * kHid + 32 * t + 8 * q);
+  }
+  __shared__ float s_t[16];
+  __shared__ int s_valid[16];
+  // Batch rows, spread over the block: thread u < 16 * kSlots fetches code
+  // `slot` of row `row` (rows past this step's count read as code 0 and
+  // train nothing); the slot-0 thread also takes the row's target.  The
+  // one-hot tile is cleared meanwhile, and filled after the barrier.
+  const int tid = threadIdx.x;
+  const int urow = tid / kSlots, uslot = tid - urow * kSlots;
+  int ucode = S;
+  if (tid < 16 * kSlots) {
+    const int b = row0 + urow;
+    int64_t drow = -1;
     if (b < ta.rows) {
       const int64_t pos = ta.start + b;
-      row = ta.perm_key ? permute_row(pos, ta.n, ta.perm_key, ta.perm_bits) : pos;
+      drow = ta.perm_key ? permute_row(pos, ta.n, ta.perm_key, ta.perm_bits) : pos;
     }
-    for (int s = 0; s < 32; ++s)
-      senv[l * 32 + s] = (row >= 0 && s < kSlots) ? ta.env[row * kSlots + s] : 0;
-    if (row >= 0 && senv[l * 32] != S - 1) {
-      valid = 1;
-      t = (ta.ea[row] - mu) / sigma;
+    ucode = drow >= 0 ? ta.env[drow * kSlots + uslot] : 0;
+    senv[urow * 32 + uslot] = (uint8_t)ucode;
+    if (uslot == 0) {
+      const bool valid = drow >= 0 && ucode != S - 1;
+      s_t[urow] = valid ? (ta.ea[drow] - mu) / sigma : 0.f;
+      s_valid[urow] = valid ? 1 : 0;
     }
-    s_t[wave][l] = t;
-    s_valid[wave][l] = valid;
+  }
+  for (int u = tid; u < 16 * ld1 / 8; u += 64 * kTrainTileWaves) *(uint4 *)(atile + 8 * u) = make_uint4(0u, 0u, 0u, 0u);
+  __syncthreads();
+  if (tid < 16 * kSlots && ucode < S) atile[urow * ld1 + uslot * S + ucode] = 0x3F80;  // bf16 1.0
+  __syncthreads();
+
+  // Layer 1, this wavefront's tile.
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < kMaxT1; ++t) {
+    if (t >= nk) break;
+    const bf16x8 a = *(const bf16x8 *)(atile + r * ld1 + 32 * t + 8 * q);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw1[t], acc, 0, 0, 0);
+  }
+  float gp1[4], gp2[4];
+  {
+    const float bias = prm[L.ob1 + col];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float z = acc[i] + bias;
+      h1s[(4 * q + i) * kLdH + col] = f2bf(gelu_f(z));
+      gp1[i] = gelu_grad_f(z);
+    }
   }
   __syncthreads();
 
-  unsigned short h1b[8][4], h2b[8][4];
-  float gp1[8][4], gp2[8][4], y[4];
-  onehot_tile(senv, atile, S, k1, l);
-  mlp_fwd16<true, true>((const uint8_t *)atile, w1t, w2t, hst, prm, L, S, k1, h1b, h2b, gp1, gp2, y);
+  // Layer 2, this wavefront's tile (A = all of h1).
+  acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const bf16x8 a = *(const bf16x8 *)(h1s + r * kLdH + 32 * t + 8 * q);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw2[t], acc, 0, 0, 0);
+  }
+  unsigned short h2b[4];
+  {
+    const float bias = prm[L.ob2 + col];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float z = acc[i] + bias;
+      h2b[i] = f2bf(gelu_f(z));
+      gp2[i] = gelu_grad_f(z);
+      h2s[(4 * q + i) * kLdH + col] = h2b[i];
+    }
+  }
+  __syncthreads();
 
-  float *part = ta.partial + (size_t)gw * (size_t)(np + 1);
+  // Output of the 16 rows (every wavefront): lane (q, r) adds h2 w3 over
+  // the 8 tiles in order, then the 16 lanes of each row group.
+  float y[4];
+  {
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < kTrainTileWaves; ++c) {
+      const float w3 = bf2f(f2bf(prm[L.ow3 + 16 * c + r]));
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part[i] = fmaf(bf2f(h2s[(4 * q + i) * kLdH + 16 * c + r]), w3, part[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float v = part[i];
+      v += __shfl_xor(v, 8, 16);
+      v += __shfl_xor(v, 4, 16);
+      v += __shfl_xor(v, 2, 16);
+      v += __shfl_xor(v, 1, 16);
+      y[i] = v + prm[L.ob3];
+    }
+  }
+
+  float *part = ta.partial + (size_t)blockIdx.x * (size_t)part_stride(np);
   const float inv_b = 2.0f / (float)max(ta.rows, 1);   // d(mean loss)/dy over this step's rows
   float dy[4];
   float lsum = 0.f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int row = 4 * q + i;
-    const float d = s_valid[wave][row] ? (y[i] - s_t[wave][row]) : 0.f;
+    const float d = s_valid[row] ? (y[i] - s_t[row]) : 0.f;
     dy[i] = d * inv_b;
     lsum += d * d;
   }
-  // Loss and output-layer gradients (rows are spread over the 4 row groups).
-  float db3 = dy[0] + dy[1] + dy[2] + dy[3];
-  db3 += __shfl_xor(db3, 16, 64);
-  db3 += __shfl_xor(db3, 32, 64);
-  lsum += __shfl_xor(lsum, 16, 64);
-  lsum += __shfl_xor(lsum, 32, 64);
-  if (l == 0) {
-    part[L.ob3] = db3;
-    part[np] = lsum;
+  if (w == 0) {
+    float db3 = dy[0] + dy[1] + dy[2] + dy[3];
+    db3 += __shfl_xor(db3, 16, 64);
+    db3 += __shfl_xor(db3, 32, 64);
+    lsum += __shfl_xor(lsum, 16, 64);
+    lsum += __shfl_xor(lsum, 32, 64);
+    if (l == 0) {
+      part[L.ob3] = db3;
+      part[np] = lsum;
+    }
   }
-  float dz2[8][4];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const float w3 = bf2f(f2bf(prm[L.ow3 + 16 * c + r]));
+  // Output-layer gradients of this tile.
+  s16x4 dz2b;
+  {
+    const float w3 = bf2f(f2bf(prm[L.ow3 + col]));
     float dw3 = 0.f, db2 = 0.f;
+    float dz2[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      dw3 = fmaf(bf2f(h2b[c][i]), dy[i], dw3);
-      dz2[c][i] = dy[i] * w3 * gp2[c][i];
-      db2 += dz2[c][i];
+      dw3 = fmaf(bf2f(h2b[i]), dy[i], dw3);
+      dz2[i] = dy[i] * w3 * gp2[i];
+      db2 += dz2[i];
     }
     dw3 += __shfl_xor(dw3, 16, 64);
     dw3 += __shfl_xor(dw3, 32, 64);
     db2 += __shfl_xor(db2, 16, 64);
     db2 += __shfl_xor(db2, 32, 64);
     if (q == 0) {
-      part[L.ow3 + 16 * c + r] = dw3;
-      part[L.ob2 + 16 * c + r] = db2;
+      part[L.ow3 + col] = dw3;
+      part[L.ob2 + col] = db2;
     }
-  }
-  // dW2[i][o] = sum_rows h1[row][i] dz2[row][o]: the 16 rows are the
-  // reduction dimension; both operands are already in the accumulator layout.
-  s16x4 dz2b[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const unsigned short hb = f2bf(dz2[c][i]);
-      dz2b[c][i] = (short)hb;
-      hst[(4 * q + i) * kLdH + 16 * c + r] = hb;
+      const unsigned short hb = f2bf(dz2[i]);
+      dz2b[i] = (short)hb;
+      dzs[(4 * q + i) * kLdH + col] = hb;
     }
+  }
+  // dW2[i][o] for this tile's outputs o: the 16 rows are the reduction
+  // dimension (A: h1 of input tile ti, B: dz2 of this tile).
 #pragma unroll
-  for (int ti = 0; ti < 8; ++ti) {
+  for (int ti = 0; ti < kTrainTileWaves; ++ti) {
     s16x4 a;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = (short)h1b[ti][i];
-#pragma unroll
-    for (int to = 0; to < 8; ++to) {
-      f32x4 cacc = {0.f, 0.f, 0.f, 0.f};
-      cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, dz2b[to], cacc, 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) part[L.oW2 + (16 * ti + 4 * q + i) * kHid + 16 * to + r] = cacc[i];
-    }
+    for (int i = 0; i < 4; ++i) a[i] = (short)h1s[(4 * q + i) * kLdH + 16 * ti + r];
+    f32x4 cacc = {0.f, 0.f, 0.f, 0.f};
+    cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, dz2b, cacc, 0, 0, 0);
+    *(f32x4 *)(part + L.oW2 + ((ti * 8 + w) * 64 + l) * 4) = cacc;
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // dh1 = dz2 W2^T (A = dz2 rows from the staging tile, B = W2 row-major).
-  f32x4 acc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+
+  // dh1 of this tile's inputs = dz2 (all outputs) W2^T.
+  acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const bf16x8 a = *(const bf16x8 *)(hst + r * kLdH + 32 * t + 8 * q);
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const bf16x8 b = *(const bf16x8 *)(w2r + (16 * c + r) * kLdH + 32 * t + 8 * q);
-      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
-    }
+    const bf16x8 a = *(const bf16x8 *)(dzs + r * kLdH + 32 * t + 8 * q);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw2r[t], acc, 0, 0, 0);
   }
-  s16x4 dz1b[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
+  s16x4 dz1b;
+  {
     float db1 = 0.f;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float dz = acc[c][i] * gp1[c][i];
+      const float dz = acc[i] * gp1[i];
       db1 += dz;
-      dz1b[c][i] = (short)f2bf(dz);
+      dz1b[i] = (short)f2bf(dz);
     }
     db1 += __shfl_xor(db1, 16, 64);
     db1 += __shfl_xor(db1, 32, 64);
-    if (q == 0) part[L.ob1 + 16 * c + r] = db1;
+    if (q == 0) part[L.ob1 + col] = db1;
   }
-  // dW1[f][n] = sum_rows x[row][f] dz1[row][n]; x from the species codes.
+  // dW1[f][n] for this tile's units n: x from the species codes.
   const int nf = k1 / 16;
   for (int tf = 0; tf < nf; ++tf) {
     const int f = 16 * tf + r;
@@ -382,13 +463,9 @@ __global__ __launch_bounds__(64 * kTrainWaves) void k_mlp_train_partial(TrainArg
       const bool one = slot < kSlots && senv[(4 * q + i) * 32 + slot] == sp;
       a[i] = (short)(one ? 0x3F80 : 0);
     }
-#pragma unroll
-    for (int tn = 0; tn < 8; ++tn) {
-      f32x4 cacc = {0.f, 0.f, 0.f, 0.f};
-      cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, dz1b[tn], cacc, 0, 0, 0);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) part[L.oW1 + (16 * tf + 4 * q + i) * kHid + 16 * tn + r] = cacc[i];
-    }
+    f32x4 cacc = {0.f, 0.f, 0.f, 0.f};
+    cacc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, dz1b, cacc, 0, 0, 0);
+    *(f32x4 *)(part + L.oW1 + ((tf * 8 + w) * 64 + l) * 4) = cacc;
   }
 }
 
@@ -406,14 +483,24 @@ __global__ __launch_bounds__(256) void k_mlp_update(unsigned char *__restrict__ 
   const int S = hdr->S, k1 = hdr->k1, np = hdr->nparams;
   const MlpLayout L = mlp_layout(S);
   const int p = blockIdx.x * 256 + threadIdx.x;
-  if (p == 0 && loss_out) {
-    float ls = 0.f;
-    for (int w = 0; w < n_waves; ++w) ls += partial[(size_t)w * (np + 1) + np];
-    *loss_out = ls * inv_rows;
-  }
+  const size_t stride = (size_t)part_stride(np);
+  // Sum over the blocks in block order, 16 reads in flight at a time.
+  auto sum_parts = [&](int idx) {
+    float acc = 0.f;
+    int w = 0;
+    for (; w + 16 <= n_waves; w += 16) {
+      float v[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) v[k] = partial[(size_t)(w + k) * stride + idx];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) acc += v[k];
+    }
+    for (; w < n_waves; ++w) acc += partial[(size_t)w * stride + idx];
+    return acc;
+  };
+  if (p == 0 && loss_out) *loss_out = sum_parts(np) * inv_rows;
   if (p >= np) return;
-  float g = 0.f;
-  for (int w = 0; w < n_waves; ++w) g += partial[(size_t)w * (np + 1) + p];
+  const float g = sum_parts(part_index(L, p));
   if (!apply) {
     grad_out[p] = g;
     return;
@@ -486,7 +573,7 @@ __global__ __launch_bounds__(256) void k_mlp_init(unsigned char *__restrict__ bl
 
 static size_t fwd_weight_bytes(int S) { return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + 2 * kHid * kLdH; }
 static size_t train_lds(int S) {
-  return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + 2 * (size_t)2 * kHid * kLdH + kTrainWaves * kWaveBytes;
+  return (size_t)2 * 16 * mlp_ld1(mlp_k1(S)) + (size_t)3 * 2 * 16 * kLdH + 16 * 32;
 }
 
 hipError_t launch_env_encode(const LatDesc *d_desc, const uint8_t *occ, const int32_t *sites,
@@ -561,21 +648,19 @@ hipError_t launch_mlp_step(unsigned char *blob, int S, const uint8_t *env, const
   ta.perm_key = perm_key;
   ta.perm_bits = perm_bits;
   ta.partial = partial;
-  const int n_waves = batch / 16;
-  const unsigned blocks = (unsigned)((n_waves + kTrainWaves - 1) / kTrainWaves);
-  hipLaunchKernelGGL(k_mlp_train_partial, dim3(blocks), dim3(64 * kTrainWaves), lds, stream, ta);
+  const unsigned blocks = (unsigned)(batch / 16);
+  hipLaunchKernelGGL(k_mlp_train_partial, dim3(blocks), dim3(64 * kTrainTileWaves), lds, stream, ta);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int np = mlp_nparams(S);
   hipLaunchKernelGGL(k_mlp_update, dim3((np + 255) / 256), dim3(256), 0, stream, blob, partial,
-                     (int)(blocks * kTrainWaves), apply, lr, beta1, beta2, eps, wd, step, grad_out,
+                     (int)blocks, apply, lr, beta1, beta2, eps, wd, step, grad_out,
                      loss_out, 1.0f / (float)std::max(rows, 1));
   return hipGetLastError();
 }
 
 size_t mlp_partial_bytes(int S, int batch) {
-  const int n_waves = ((batch / 16 + kTrainWaves - 1) / kTrainWaves) * kTrainWaves;
-  return sizeof(float) * (size_t)n_waves * (size_t)(mlp_nparams(S) + 1);
+  return sizeof(float) * (size_t)(batch / 16) * (size_t)part_stride(mlp_nparams(S));
 }
 
 }  // namespace akmc
