@@ -338,8 +338,14 @@ __global__ __launch_bounds__(kSweepThreads) void k_rates_all(const LatDesc *__re
     }
   }
 
-  // One workgroup per brick of a 3-D grid of bricks.
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = blockIdx.z * TZ;
+  // One workgroup per brick, y fastest: workgroups are dealt to the 8 XCDs
+  // in turn, each with an L2 of its own, so y-neighbouring bricks land on
+  // different XCDs and a lattice row (its x run of one cache line or more)
+  // is fetched by the XCD whose bricks hold it, plus the two whose y halos
+  // reach it, instead of by every XCD whose brick holds a piece of it.
+  const int nbx = (lx + TX - 1) / TX, nby = (ly + TY - 1) / TY;
+  const int y0 = (int)(blockIdx.x % nby) * TY, x0 = (int)(blockIdx.x / nby % nbx) * TX;
+  const int z0 = (int)(blockIdx.x / (nby * nbx)) * TZ;
 
   // Phase 1: occupancy brick of both sublattices, as 4*species (the shift of
   // that species' count nibble).  One conditional wrap per axis suffices
@@ -659,8 +665,7 @@ template <int TX, int TY, int TZ, int S, class Real>
 static hipError_t launch_sweep(const LatDesc *d_desc, const LatDesc &h, const uint8_t *occ,
                                void *rates, void *ea, hipStream_t stream, const LaunchTiming *tm) {
   using Sh = SweepShape<TX, TY, TZ>;
-  const dim3 tiles((unsigned)((h.lx + TX - 1) / TX), (unsigned)((h.ly + TY - 1) / TY),
-                   (unsigned)((h.lz + TZ - 1) / TZ));
+  const dim3 tiles((unsigned)(((h.lx + TX - 1) / TX) * ((h.ly + TY - 1) / TY) * ((h.lz + TZ - 1) / TZ)));
   const size_t lds = Sh::lds_bytes(S, sizeof(Real), ea != nullptr);
   auto k = ea ? k_rates_all<TX, TY, TZ, S, Real, true> : k_rates_all<TX, TY, TZ, S, Real, false>;
   if (lds > 65536) {
