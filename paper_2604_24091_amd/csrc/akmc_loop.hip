@@ -334,7 +334,7 @@ struct Runner {
   static constexpr int FN = FAR ? kFootFarN + 1 : LRN ? kFootNL : kFootN;
   static constexpr int FM = (FN + 7) / 8;
   static constexpr int BB = FAR ? kBoxBytesFar : kBoxBytes;
-  static constexpr int REACH = FAR ? 6 : LRN ? 5 : 4;
+  static constexpr int REACH = FAR ? 6 : LRN ? 5 : 4;  // footprint reach + 1: bounds i from j's side
   LoopArgs a;
   Group<G> gp;
   int foot[FM];
@@ -809,6 +809,49 @@ struct Runner {
     return fresh;
   }
 
+  // The tree paths of the na <= 8 refreshed slots aff[0 .. na) at once (a
+  // 64-lane group with tree levels 2 and 3 in registers): subgroup p
+  // re-sums the level-1 group of slot aff[p] from the slot totals, the
+  // register levels take every new group total and are re-summed once.
+  // Each node is the same fixed function of its children as with one path
+  // at a time (a group listed twice is summed twice, to the same values).
+  __device__ double update_paths_regs(int na) {
+    const int gl = gp.gl, c = gl & 7, p = gl >> 3;
+    const int g1 = s.aff[min(p, na - 1)] >> 3;
+    const int cnt1 = min(8, nv - 8 * g1);
+    const double xr = s.part[(8 * g1 + min(c, cnt1 - 1)) * 8 + 7];  // unpredicated
+    const double p1 = subgroup_prefix(c < cnt1 ? xr : 0.0, c);
+    if (p < na && c < cnt1) Q(1)[8 * g1 + c] = p1;
+    for (int pp = 0; pp < na; ++pp) {
+      const int gg = __builtin_amdgcn_readlane(g1, 8 * pp);
+      const int cc = min(8, nv - 8 * gg);
+      const double tot = lane_value(p1, 8 * pp + cc - 1);
+      t2 = gl == gg ? tot : t2;
+    }
+    q2 = subgroup_prefix(t2, c);
+    const int n2 = nl(2);
+    if (gl < n2) Q(2)[gl] = q2;
+    double fresh;
+    if (nlev == 2) {
+      top_q = gl < 8 ? q2 : 0.0;
+      fresh = lane_value(q2, n2 - 1);
+    } else {
+      for (int pp = 0; pp < na; ++pp) {
+        const int gg = __builtin_amdgcn_readlane(g1, 8 * pp) >> 3;
+        const int cc = min(8, n2 - 8 * gg);
+        const double tot = lane_value(q2, 8 * gg + cc - 1);
+        t3 = gl == gg ? tot : t3;
+      }
+      q3 = subgroup_prefix(t3, c);
+      const int n3 = nl(3);
+      if (gl < n3) Q(3)[gl] = q3;
+      top_q = gl < 8 ? q3 : 0.0;
+      fresh = lane_value(q3, n3 - 1);
+    }
+    gsync();
+    return fresh;
+  }
+
   // One selection step at level l >= 2 from the registers (a 64-lane
   // group): the children of the node whose first child is `base` sit in
   // lanes base .. base+cnt-1 of q (partials) and t (values).  The same
@@ -1125,16 +1168,22 @@ struct Runner {
           for (int u = 0; u < 4; ++u) qp[u] = s.pos[min(b0 + u * G + gl, nv - 1)];  // unpredicated
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
-            // |d| by sum-of-absolute-differences, then the periodic image
-            int dx = (int)__sad(pos_x(qp[u]), X, 0u), dy = (int)__sad(pos_y(qp[u]), Y, 0u),
-                dz = (int)__sad(pos_z(qp[u]), Z, 0u);
+            // |d| to i and to j by sum-of-absolute-differences, then the
+            // periodic image
+            const int px = pos_x(qp[u]), py = pos_y(qp[u]), pz = pos_z(qp[u]);
+            int dx = (int)__sad(px, X, 0u), dy = (int)__sad(py, Y, 0u), dz = (int)__sad(pz, Z, 0u);
+            int ex = (int)__sad(px, JX, 0u), ey = (int)__sad(py, JY, 0u), ez = (int)__sad(pz, JZ, 0u);
             dx = min(dx, g.X2 - dx);
             dy = min(dy, g.Y2 - dy);
             dz = min(dz, g.Z2 - dz);
-            // reach: a candidate's bonds lie within 3 half-cells of its
-            // vacancy (5 with pairs out to 6.0 A), an observation within 4,
-            // so i or j changes them only within REACH half-cells of i
-            hit[u] = b0 + u * G + gl < nv && max(dx, max(dy, dz)) <= REACH;
+            ex = min(ex, g.X2 - ex);
+            ey = min(ey, g.Y2 - ey);
+            ez = min(ez, g.Z2 - ez);
+            // a candidate's bonds lie within 3 half-cells of its vacancy
+            // (5 with pairs out to 6.0 A), an observation within 4: REACH - 1
+            // per axis; the slot is stale only if i or j lies that close
+            hit[u] = b0 + u * G + gl < nv &&
+                     (max(dx, max(dy, dz)) < REACH || max(ex, max(ey, ez)) < REACH);
           }
         };
         // The grid first: lane b < 8 reads the cell of (X +- R, Y +- R,
@@ -1225,16 +1274,7 @@ struct Runner {
       } else {
         refresh(na, si, sj, A, false, nullptr, rec);
         if (G == 64 && nlev >= 2 && na <= 8) {
-          // A few refreshed slots: their tree paths one after the other
-          // (each re-sums its groups from the current totals, so the last
-          // update leaves every changed node equal to the level-by-level
-          // fold).
-          for (int p = 0; p < na; ++p) {
-            const int u = __builtin_amdgcn_readfirstlane(s.aff[p]);
-            const int ug = 8 * (u >> 3) + (gl & 7);
-            const double xu = gl < 8 && ug < nv ? s.part[ug * 8 + 7] : 0.0;
-            gtot = update_path_regs(u, lane_value(xu, u & 7), xu);
-          }
+          gtot = update_paths_regs(na);
         } else {
           update_tree(na);
           gtot = gamma_tot();
