@@ -1207,22 +1207,10 @@ struct Runner {
             grid_inc(vg, cj);
           }
         }
-        bool others = false;
-        for (int b0 = 0; scan && b0 < nv; b0 += 4 * G) {
-          bool hit[4];
-          hits(b0, hit);
-          bool oth = false;
-#pragma unroll
-          for (int u = 0; u < 4; ++u) oth = oth || (hit[u] && b0 + u * G + gl != v);
-          others = others || gp.ballot(oth) != 0;
-        }
-        if (!others) {
-          na = 1;
-          if (MLP || LRN) {
-            if (gl == 0) s.aff[0] = v;
-            gsync();
-          }
-        } else {
+        // One pass builds the ordered list of every slot the exact test
+        // hits (v among them); only v means the fast path.
+        na = 1;
+        if (scan) {
           na = 0;
           for (int b0 = 0; b0 < nv; b0 += 4 * G) {
             bool hit[4];
@@ -1234,6 +1222,9 @@ struct Runner {
               na += __popcll(m);
             }
           }
+          gsync();
+        } else if (MLP || LRN) {
+          if (gl == 0) s.aff[0] = v;
           gsync();
         }
       }
