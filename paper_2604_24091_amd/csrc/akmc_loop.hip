@@ -315,12 +315,101 @@ struct MlpLds {
   uint8_t *senv;
   float *yb;
   float *pb;  // biases b1, b2, output weights w3 and bias b3 (128, 128, 128, 1)
-  unsigned short *atile;  // one-hot input tile, 16 rows of pitch mlp_ld1(k1)
+  unsigned short *atile;  // one-hot input tile, 16 rows of pitch mlp_ld1(k1); then layer 2's output
+  int *cmd;               // to the helper wavefronts: 1 = a tile, 0 = the end of the launch
 };
 
 __host__ __device__ inline size_t mlp_loop_lds_bytes(int S) {
   return (size_t)2 * kHid * mlp_ld1(mlp_k1(S)) + (size_t)2 * kHid * kLdH + 64 * 32 + 2 * 16 * kLdH + 64 * 4 +
-         (3 * kHid + 1) * 4 + 16 + (size_t)2 * 16 * mlp_ld1(mlp_k1(S));
+         (3 * kHid + 1) * 4 + 16 + (size_t)2 * 16 * mlp_ld1(mlp_k1(S)) + 16;
+}
+
+// The surrogate's LDS area of the event loop, at b (after the lattice).
+__device__ inline MlpLds mlp_lds_at(unsigned char *b, int k1) {
+  MlpLds ml;
+  ml.w1t = (unsigned short *)b;
+  ml.w2t = ml.w1t + kHid * mlp_ld1(k1);
+  ml.senv = (uint8_t *)(ml.w2t + kHid * kLdH);
+  ml.hst = (unsigned short *)(ml.senv + 64 * 32);
+  ml.yb = (float *)(ml.hst + 16 * kLdH);
+  ml.pb = ml.yb + 64;
+  ml.atile = (unsigned short *)(((uintptr_t)(ml.pb + 3 * kHid + 1) + 15) & ~(uintptr_t)15);
+  ml.cmd = (int *)(ml.atile + 16 * mlp_ld1(k1));
+  return ml;
+}
+
+// Wavefronts of the surrogate loop's workgroup: the event loop runs on the
+// first; all of them share each 16-row tile of the forward.
+constexpr int kMlpWaves = 4;
+
+// One 16-row tile of the surrogate forward (the one-hot inputs in atile) by
+// the kMlpWaves wavefronts of the workgroup: wavefront w takes the kCpw
+// hidden-unit tiles c = kCpw*w .. of both layers (the same matrix-core products,
+// bias and GELU as the one-wavefront forward, h1 shared in hst, h2 written
+// over atile); then wavefront w forms the outputs of rows 4*(l/16) + i for
+// its i exactly as the one-wavefront forward does (each lane over c = 0..7
+// in order, then its 16-lane row group) and stores them at yout[row].
+// Every wavefront of the workgroup calls it, between the same barriers.
+__device__ inline void mlp_tile_waves(const MlpLds &ml, int k1, int w, float *yout) {
+  constexpr int kCpw = kHid / 16 / kMlpWaves;  // hidden-unit tiles per wavefront
+  static_assert(kCpw * kMlpWaves == kHid / 16, "whole hidden-unit tiles per wavefront");
+  const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
+  const int ld1 = mlp_ld1(k1), nk = k1 / 32;
+  f32x4 acc[kCpw];
+#pragma unroll
+  for (int cc = 0; cc < kCpw; ++cc) acc[cc] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < nk; ++t) {
+    const bf16x8 a = *(const bf16x8 *)(ml.atile + r * ld1 + 32 * t + 8 * q);
+#pragma unroll
+    for (int cc = 0; cc < kCpw; ++cc) {
+      const bf16x8 b = *(const bf16x8 *)(ml.w1t + (16 * (kCpw * w + cc) + r) * ld1 + 32 * t + 8 * q);
+      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cc], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < kCpw; ++cc) {
+    const int c = kCpw * w + cc;
+    const float bias = ml.pb[16 * c + r];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ml.hst[(4 * q + i) * kLdH + 16 * c + r] = f2bf(gelu_f(acc[cc][i] + bias));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int cc = 0; cc < kCpw; ++cc) acc[cc] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const bf16x8 a = *(const bf16x8 *)(ml.hst + r * kLdH + 32 * t + 8 * q);
+#pragma unroll
+    for (int cc = 0; cc < kCpw; ++cc) {
+      const bf16x8 b = *(const bf16x8 *)(ml.w2t + (16 * (kCpw * w + cc) + r) * kLdH + 32 * t + 8 * q);
+      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cc], 0, 0, 0);
+    }
+  }
+  unsigned short *h2 = ml.atile;  // every wavefront has read its inputs (barrier above)
+#pragma unroll
+  for (int cc = 0; cc < kCpw; ++cc) {
+    const int c = kCpw * w + cc;
+    const float bias = ml.pb[kHid + 16 * c + r];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) h2[(4 * q + i) * kLdH + 16 * c + r] = f2bf(gelu_f(acc[cc][i] + bias));
+  }
+  __syncthreads();
+  constexpr int kIpw = 4 / kMlpWaves;  // output rows per lane and wavefront
+  static_assert(kIpw * kMlpWaves == 4, "the four rows of a lane over the wavefronts");
+#pragma unroll
+  for (int ii = 0; ii < kIpw; ++ii) {
+    const int i = kIpw * w + ii;
+    float part = 0.f;
+#pragma unroll
+    for (int c = 0; c < kHid / 16; ++c)
+      part = fmaf(bf2f(h2[(4 * q + i) * kLdH + 16 * c + r]), bf2f(f2bf(ml.pb[2 * kHid + 16 * c + r])), part);
+    part += __shfl_xor(part, 8, 16);
+    part += __shfl_xor(part, 4, 16);
+    part += __shfl_xor(part, 2, 16);
+    part += __shfl_xor(part, 1, 16);
+    if (r == 0) yout[4 * q + i] = part + ml.pb[3 * kHid];
+  }
+  __syncthreads();
 }
 
 // KL: the most tree levels of any lattice of the launch (at most
@@ -405,14 +494,7 @@ struct Runner {
       prm = (const float *)(a.mlp_blob + mlay.params);
       mu = hdr->mu;
       sigma = hdr->sigma;
-      unsigned char *b = lds + L.bytes;
-      ml.w1t = (unsigned short *)b;
-      ml.w2t = ml.w1t + kHid * mlp_ld1(k1);
-      ml.senv = (uint8_t *)(ml.w2t + kHid * kLdH);
-      ml.hst = (unsigned short *)(ml.senv + 64 * 32);
-      ml.yb = (float *)(ml.hst + 16 * kLdH);
-      ml.pb = ml.yb + 64;
-      ml.atile = (unsigned short *)(((uintptr_t)(ml.pb + 3 * kHid + 1) + 15) & ~(uintptr_t)15);
+      ml = mlp_lds_at(lds + L.bytes, k1);
       stage_rows(ml.w1t, (const unsigned short *)(a.mlp_blob + mlay.w1t), kHid, k1, mlp_ld1(k1), gp.gl, G);
       stage_rows(ml.w2t, (const unsigned short *)(a.mlp_blob + mlay.w2t), kHid, kHid, kLdH, gp.gl, G);
       seen = 0u;
@@ -597,16 +679,12 @@ struct Runner {
     gsync();
     const int ntiles = (np * 8 + 15) / 16;
     for (int t = 0; t < ntiles; ++t) {
-      unsigned short h1b[8][4], h2b[8][4];
-      float gp1[8][4], gp2[8][4], y[4];
       onehot_tile(ml.senv + t * 16 * 32, ml.atile, S, k1, gp.gl);
-      mlp_fwd16<false, true>((const uint8_t *)ml.atile, ml.w1t, ml.w2t, ml.hst, ml.pb, play, S, k1, h1b, h2b,
-                       gp1, gp2, y);
-      if ((gp.gl & 15) == 0)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) ml.yb[t * 16 + 4 * (gp.gl >> 4) + i] = y[i];
+      // the helper wavefronts take their share of the tile
+      if (gp.gl == 0) *ml.cmd = 1 + t;
+      __syncthreads();
+      mlp_tile_waves(ml, k1, 0, ml.yb + 16 * t);
     }
-    gsync();
     double r = 0.0;
     const bool live = q < np && A != V;
     if (q < np) s.spec[vv * 8 + k] = (uint8_t)A;
@@ -1307,10 +1385,24 @@ struct Runner {
 
 template <int G, int WAVES, bool FP32, bool MLP = false, int KL = kMaxLevels, bool LRN = false,
           bool FAR = false>
-__global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayout L) {
+__global__ __launch_bounds__(64 * (MLP ? kMlpWaves : WAVES)) void k_event_loop(LoopArgs a, GroupLayout L) {
   using Real = typename std::conditional<FP32, float, double>::type;
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (MLP && wave != 0) {
+    // A helper wavefront of the surrogate loop: its share of each tile the
+    // event loop (wavefront 0) announces, until the end of the launch.
+    static_assert(!MLP || (G == 64 && WAVES == 1), "the surrogate loop runs one 64-lane group");
+    const int k1 = ((const MlpHeader *)a.mlp_blob)->k1;
+    const MlpLds ml = mlp_lds_at(lds + L.bytes, k1);
+    for (;;) {
+      __syncthreads();
+      const int cmd = *ml.cmd;  // 1 + the tile's place in the pass, 0 at the end
+      if (cmd == 0) break;
+      mlp_tile_waves(ml, k1, wave, ml.yb + 16 * (cmd - 1));
+    }
+    return;
+  }
   Group<G> gp;
   gp.gw = lane / G;
   gp.gl = lane % G;
@@ -1365,6 +1457,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_event_loop(LoopArgs a, GroupLayo
     int lat = a.order[idx];
     if (G == 64) lat = __builtin_amdgcn_readfirstlane(lat);
     run.run(lat);
+  }
+  if (MLP) {
+    // releases the helper wavefronts
+    if (lane == 0) *run.ml.cmd = 0;
+    __syncthreads();
   }
 }
 
@@ -1436,7 +1533,7 @@ hipError_t launch_event_loop_mlp(const LoopArgs &a, int refresh_full, int n_spec
   auto kern = k_event_loop<64, 1, true, true>;
   e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(1), dim3(64), lds, stream, b, L);
+  hipLaunchKernelGGL(kern, dim3(1), dim3(64 * kMlpWaves), lds, stream, b, L);
   return hipGetLastError();
 }
 
