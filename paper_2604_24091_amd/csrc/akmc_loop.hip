@@ -459,6 +459,8 @@ struct Runner {
   double *wq;     // [64] selection weights of one refresh pass, lane order
   uint8_t *obs;   // [8][64] observation codes of one refresh pass
   float *hbuf;    // [64] activation staging
+  int *lcmd;      // to the second wavefront (both networks): slots of a pass, 0 at the end
+  bool split;     // the Poisson network runs on the second wavefront
   int obs_src;    // box byte of this lane's observation neighbour
 
   __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
@@ -474,9 +476,11 @@ struct Runner {
       wq = gv + a.nv_max;
       hbuf = (float *)(wq + 64);
       obs = (uint8_t *)(hbuf + 64);
-      b = obs + 8 * kObsN;
+      lcmd = (int *)(obs + 8 * kObsN + 64 * 4);  // after the second wavefront's hbuf
+      b = (unsigned char *)(lcmd + 4);
       has_pol = a.pol_blob != nullptr;
       has_pt = a.pt_blob != nullptr;
+      split = has_pol && has_pt && blockDim.x > 64;
       obs_src = kObsSrc.b[gp.gl];
       inv_tau = a.inv_tau;
       if (has_pol) {
@@ -776,6 +780,14 @@ struct Runner {
     if (q < np && k == 7) pg[vv] = pfx;
     for (int qq = 0; qq < np; ++qq) obs[qq * kObsN + gl] = s.box[qq * BB + obs_src] >> 2;
     gsync();
+    if (split) {
+      // the second wavefront evaluates the Poisson network of these slots
+      if (gl == 0) {
+        lcmd[0] = np;
+        lcmd[1] = p0;
+      }
+      __syncthreads();
+    }
     for (int qq = 0; qq < np; ++qq) {
       const int v_q = s.aff[p0 + qq];
       if (has_pol) {
@@ -785,11 +797,12 @@ struct Runner {
           wq[qq * 8 + gl] = ok ? exp((double)(z * inv_tau)) : 0.0;
         }
       }
-      if (has_pt) {
+      if (has_pt && !split) {
         const float gval = patch_forward(pt, obs + qq * kObsN, hbuf, gl);
         if (gl == 0) gv[v_q] = (double)gval;
       }
     }
+    if (split) __syncthreads();  // gv of these slots written
     gsync();
     return has_pol ? (q < np ? wq[gl] : 0.0) : r;
   }
@@ -1385,10 +1398,37 @@ struct Runner {
 
 template <int G, int WAVES, bool FP32, bool MLP = false, int KL = kMaxLevels, bool LRN = false,
           bool FAR = false>
-__global__ __launch_bounds__(64 * (MLP ? kMlpWaves : WAVES)) void k_event_loop(LoopArgs a, GroupLayout L) {
+__global__ __launch_bounds__(64 * (MLP ? kMlpWaves : LRN ? 2 : WAVES)) void k_event_loop(LoopArgs a, GroupLayout L) {
   using Real = typename std::conditional<FP32, float, double>::type;
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (LRN && wave != 0) {
+    // The second wavefront of a learned loop with both networks: the
+    // Poisson network of each refresh pass the first one announces (the
+    // same forward, on its own activation buffer), until the end.
+    static_assert(!LRN || (G == 64 && WAVES == 1), "the learned loop runs one 64-lane group");
+    const Lds<Real> sl = carve<Real>(lds, L);
+    unsigned char *b = lds + L.bytes;
+    double *gv = (double *)b + a.nv_max;
+    const uint8_t *obs = (const uint8_t *)((double *)b + 2 * a.nv_max + 64) + 64 * 4;
+    float *hbuf = (float *)(obs + 8 * kObsN);
+    int *lcmd = (int *)(hbuf + 64);
+    unsigned char *nets = (unsigned char *)(lcmd + 4);
+    const PatchHeader *ph = (const PatchHeader *)a.pol_blob;
+    const PatchNet pt = patch_view(a.pt_blob, nets + patch_lds_bytes(ph->S, ph->H, ph->n_out));
+    for (;;) {
+      __syncthreads();
+      const int np = lcmd[0];
+      if (np == 0) break;
+      const int p0 = lcmd[1];
+      for (int qq = 0; qq < np; ++qq) {
+        const float gval = patch_forward(pt, obs + qq * kObsN, hbuf, lane);
+        if (lane == 0) gv[sl.aff[p0 + qq]] = (double)gval;
+      }
+      __syncthreads();
+    }
+    return;
+  }
   if (MLP && wave != 0) {
     // A helper wavefront of the surrogate loop: its share of each tile the
     // event loop (wavefront 0) announces, until the end of the launch.
@@ -1461,6 +1501,10 @@ __global__ __launch_bounds__(64 * (MLP ? kMlpWaves : WAVES)) void k_event_loop(L
   if (MLP) {
     // releases the helper wavefronts
     if (lane == 0) *run.ml.cmd = 0;
+    __syncthreads();
+  }
+  if (LRN && run.split) {
+    if (lane == 0) run.lcmd[0] = 0;
     __syncthreads();
   }
 }
@@ -1566,7 +1610,7 @@ hipError_t launch_event_loop_far(const LoopArgs &a, int precision, int refresh_f
 size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3],
                                 const int pt_dims[3], int grid_words) {
   const GroupLayout L = make_layout(nv_max, 64, precision == AKMC_FP32, 0, grid_words);
-  size_t b = (size_t)L.bytes + 16 * (size_t)nv_max + 8 * 64 + 4 * 64 + kObsN * 8;
+  size_t b = (size_t)L.bytes + 16 * (size_t)nv_max + 8 * 64 + 4 * 64 + kObsN * 8 + 4 * 64 + 16;
   if (pol_dims) b += (size_t)patch_lds_bytes(pol_dims[0], pol_dims[1], pol_dims[2]);
   if (pt_dims) b += (size_t)patch_lds_bytes(pt_dims[0], pt_dims[1], pt_dims[2]);
   return b;
@@ -1580,7 +1624,9 @@ static hipError_t launch_lrn(const LoopArgs &a, size_t lds, hipStream_t stream) 
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(kern, dim3(1), dim3(64), lds, stream, a, L);
+  // with both networks a second wavefront evaluates the Poisson network
+  const int threads = a.pol_blob && a.pt_blob ? 128 : 64;
+  hipLaunchKernelGGL(kern, dim3(1), dim3(threads), lds, stream, a, L);
   return hipGetLastError();
 }
 

@@ -120,6 +120,24 @@ struct PatchNet {
 // nthreads threads; returns the LDS view.  The bfloat16 weights are the
 // upper halves of their binary32 values (exact: the blob holds bfloat16
 // values).
+// The LDS view of a network that patch_stage placed at `dst` (no copy).
+__device__ inline PatchNet patch_view(const unsigned char *blob, unsigned char *dst) {
+  const PatchHeader *h = (const PatchHeader *)blob;
+  const int S = h->S, H = h->H, no = h->n_out;
+  const int ld = patch_ldt(H), nw1 = patch_w1_elems(S, H);
+  PatchNet n;
+  n.w1 = (const unsigned short *)dst;
+  n.w2t = n.w1 + nw1;
+  n.w3t = n.w2t + H * ld;
+  n.b1 = (const float *)(dst + ((2 * (nw1 + (H + no) * ld) + 15) & ~15));
+  n.b2 = n.b1 + H;
+  n.b3 = n.b1 + 2 * H;
+  n.S = S;
+  n.H = H;
+  n.n_out = no;
+  return n;
+}
+
 __device__ inline PatchNet patch_stage(const unsigned char *blob, unsigned char *dst, int tid,
                                        int nthreads) {
   const PatchHeader *h = (const PatchHeader *)blob;
