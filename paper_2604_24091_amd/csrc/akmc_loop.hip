@@ -157,6 +157,39 @@ constexpr BondFar make_bond_far() {
 }
 // Used in fully unrolled loops only, so every entry folds into an immediate.
 constexpr BondFar kBondFar = make_bond_far();
+__constant__ BondFar kBondFarDev = make_bond_far();  // for per-lane (runtime) indices
+
+// The 64 bonds of a jump's site in 8 groups of one shell each (the 24 of
+// shell 3 in three groups), for the 8 lanes that count one candidate
+// together: group p holds bond indices m[p][0..) (-1 past the end).
+constexpr int kFarGroupShell[8] = {0, 1, 2, 3, 3, 3, 4, 5};
+constexpr int kFarGroupMax = 12;
+struct FarGroups {
+  int8_t m[8][kFarGroupMax];
+};
+constexpr FarGroups make_far_groups() {
+  FarGroups g{};
+  int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int p = 0; p < 8; ++p)
+    for (int u = 0; u < kFarGroupMax; ++u) g.m[p][u] = -1;
+  for (int m = 0; m < kObsN; ++m)
+    for (int p = 0; p < 8; ++p)
+      if (kFarGroupShell[p] == kBondFar.sh[m] && cnt[p] < (p == 2 ? 12 : 8)) {
+        g.m[p][cnt[p]++] = (int8_t)m;
+        break;
+      }
+  return g;
+}
+constexpr bool far_groups_cover() {
+  const FarGroups g = make_far_groups();
+  int n = 0;
+  for (int p = 0; p < 8; ++p)
+    for (int u = 0; u < kFarGroupMax; ++u) n += g.m[p][u] >= 0;
+  return n == kObsN;
+}
+static_assert(far_groups_cover(), "every bond in one group");
+__constant__ FarGroups kFarGroups = make_far_groups();
+constexpr int kFarNone = 0x7fff;  // no bond at this place of a group
 
 // Box byte of each observation neighbour: inside the 7x7x7 box, or the far
 // slot of an axis site 4 half-cells away.
@@ -305,6 +338,65 @@ __device__ __forceinline__ double eval_box6(const uint8_t *box, int k, int V, in
   const Real ea = e0[A] + Real(0.5) * de;
   ea_out = ea;
   return (double)rate_from_barrier(ea, nu, kT);
+}
+
+// The same rate on a full wavefront: lane 8k + p counts bond group p of
+// candidate k (fo: this lane's group offsets, kFarNone past its end), the
+// count words are collected in lane 8k by DPP row shifts (integer sums, so
+// the counts are those eval_box6 forms) and lane 8k runs the six-shell chain.
+// Returns the rate, species and barrier of candidate gl in lanes gl < 8.
+// Every lane of the wavefront must call it.
+template <int SHR>
+__device__ __forceinline__ uint64_t row_shl64(uint64_t x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, 0x100 + SHR, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), 0x100 + SHR, 0xF, 0xF, false);
+  return (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
+}
+template <class Real>
+__device__ __forceinline__ double eval_box6_wave(const uint8_t *box, int gl, const int (&fo)[kFarGroupMax],
+                                                 int V, int S, const Real *D1, const Real *D2, const Real *Dx,
+                                                 const Real *e0, Real nu, Real kT, int &A_out, Real &ea_out) {
+  const int k = gl >> 3;
+  const int dk = dir_sx(k) + 11 * dir_sy(k) + 121 * dir_sz(k);
+  const int jb = kBoxCF + dk;
+  uint64_t ci = 0, cj = 0;
+#pragma unroll
+  for (int u = 0; u < kFarGroupMax; ++u) {
+    const int off = fo[u];
+    if (off == kFarNone) continue;
+    const uint64_t bi = 1ull << (box[kBoxCF + off] << 1);
+    const uint64_t bj = 1ull << (box[jb + off] << 1);
+    if (off != dk) ci += bi;
+    if (off != -dk) cj += bj;
+  }
+  // lane 8k collects groups 1..7 (group 0 is its own)
+  uint64_t wi[6], wj[6];
+  wi[0] = ci;
+  wj[0] = cj;
+  wi[1] = row_shl64<1>(ci);
+  wj[1] = row_shl64<1>(cj);
+  wi[2] = row_shl64<2>(ci);
+  wj[2] = row_shl64<2>(cj);
+  wi[3] = row_shl64<3>(ci) + row_shl64<4>(ci) + row_shl64<5>(ci);
+  wj[3] = row_shl64<3>(cj) + row_shl64<4>(cj) + row_shl64<5>(cj);
+  wi[4] = row_shl64<6>(ci);
+  wj[4] = row_shl64<6>(cj);
+  wi[5] = row_shl64<7>(ci);
+  wj[5] = row_shl64<7>(cj);
+  const int A = box[jb] >> 2;
+  double r = 0.0;
+  Real ea = Real(__builtin_huge_valf());
+  if ((gl & 7) == 0 && A != V) {
+    const Real de = delta_e_counts6<Real>(wi, wj, S, D1 + 8 * A, D2 + 8 * A, Dx, A);
+    ea = e0[A] + Real(0.5) * de;
+    r = (double)rate_from_barrier(ea, nu, kT);
+  }
+  // candidate k's results from lane 8k to lane k
+  const int src = 8 * (gl & 7);
+  r = __hiloint2double(__shfl(__double2hiint(r), src), __shfl(__double2loint(r), src));
+  ea_out = __shfl(ea, src);
+  A_out = __shfl(A, src);
+  return r;
 }
 
 // LDS of the learned barrier (one group per block): bf16 weights, the
@@ -462,6 +554,7 @@ struct Runner {
   int *lcmd;      // to the second wavefront (both networks): slots of a pass, 0 at the end
   bool split;     // the Poisson network runs on the second wavefront
   int obs_src;    // box byte of this lane's observation neighbour
+  int fo[FAR ? kFarGroupMax : 1];  // six shells: this lane's bond group (box offsets)
 
   __device__ Runner(const LoopArgs &a_, const GroupLayout &L, const Group<G> &gp_,
                     const int (&foot_)[FM], unsigned char *lds)
@@ -1028,6 +1121,13 @@ struct Runner {
     if (gl < 8) s.e0[gl] = fp32 ? (Real)d->e0f[gl] : (Real)d->e0[gl];
     if (FAR)
       for (int x = gl; x < 256; x += G) s.Dx[x] = fp32 ? (Real)(&d->Dxf[0][0])[x] : (Real)(&d->Dx[0][0])[x];
+    if constexpr (FAR && G == 64) {
+#pragma unroll
+      for (int u = 0; u < kFarGroupMax; ++u) {
+        const int m = kFarGroups.m[gl & 7][u];
+        fo[u] = m >= 0 ? kBondFarDev.off[m] : kFarNone;
+      }
+    }
     nu = fp32 ? (Real)d->nuf : (Real)d->nu;
     kT = fp32 ? (Real)d->kTf : (Real)d->kT;
     const uint64_t seed = d->seed, stream = d->stream;
@@ -1341,12 +1441,26 @@ struct Runner {
         if (gl < 8) {
           int Ak;
           Real ea;
-          if (FAR)
+          if (FAR && G < 64)
             r = eval_box6<Real>(s.box, kk, V, S, s.D1, s.D2, s.Dx, s.e0, nu, kT, Ak, ea);
-          else
+          else if (!FAR)
             r = eval_box<Real>(s.box, kk, V, s.D1, s.D2, s.e0, nu, kT, Ak, ea);
-          s.spec[v * 8 + kk] = (uint8_t)Ak;
-          if (eat) eat[v * 8 + kk] = ea;
+          if (!FAR || G < 64) {
+            s.spec[v * 8 + kk] = (uint8_t)Ak;
+            if (eat) eat[v * 8 + kk] = ea;
+          }
+        }
+        if constexpr (FAR && G == 64) {
+          // six shells: all 64 lanes count, 8 per candidate
+          int Ak;
+          Real ea;
+          r = eval_box6_wave<Real>(s.box, gl, fo, V, S, s.D1, s.D2, s.Dx, s.e0, nu, kT, Ak, ea);
+          if (gl < 8) {
+            s.spec[v * 8 + kk] = (uint8_t)Ak;
+            if (eat) eat[v * 8 + kk] = ea;
+          } else {
+            r = 0.0;
+          }
         }
         if (LRN) r = learned_pass(1, 0, gl >> 3, kk, r, v);
         const double pfx = subgroup_prefix(r, kk);
