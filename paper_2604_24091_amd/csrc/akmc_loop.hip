@@ -1512,15 +1512,15 @@ struct Runner {
 
 template <int G, int WAVES, bool FP32, bool MLP = false, int KL = kMaxLevels, bool LRN = false,
           bool FAR = false>
-__global__ __launch_bounds__(64 * (MLP ? kMlpWaves : LRN ? 2 : WAVES)) void k_event_loop(LoopArgs a, GroupLayout L) {
+__global__ __launch_bounds__(64 * (MLP ? kMlpWaves : WAVES)) void k_event_loop(LoopArgs a, GroupLayout L) {
   using Real = typename std::conditional<FP32, float, double>::type;
   extern __shared__ __align__(16) unsigned char lds[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (LRN && wave != 0) {
-    // The second wavefront of a learned loop with both networks: the
-    // Poisson network of each refresh pass the first one announces (the
+  if (LRN && WAVES == 2 && wave != 0) {
+    // The second wavefront of a learned loop with both networks (WAVES = 2):
+    // the Poisson network of each refresh pass the first one announces (the
     // same forward, on its own activation buffer), until the end.
-    static_assert(!LRN || (G == 64 && WAVES == 1), "the learned loop runs one 64-lane group");
+    static_assert(!LRN || (G == 64 && WAVES <= 2), "the learned loop runs one 64-lane group");
     const Lds<Real> sl = carve<Real>(lds, L);
     unsigned char *b = lds + L.bytes;
     double *gv = (double *)b + a.nv_max;
@@ -1617,7 +1617,7 @@ __global__ __launch_bounds__(64 * (MLP ? kMlpWaves : LRN ? 2 : WAVES)) void k_ev
     if (lane == 0) *run.ml.cmd = 0;
     __syncthreads();
   }
-  if (LRN && run.split) {
+  if (LRN && WAVES == 2 && run.split) {
     if (lane == 0) run.lcmd[0] = 0;
     __syncthreads();
   }
@@ -1730,18 +1730,22 @@ size_t event_loop_lrn_lds_bytes(int nv_max, int precision, const int pol_dims[3]
   return b;
 }
 
-template <bool FP32>
-static hipError_t launch_lrn(const LoopArgs &a, size_t lds, hipStream_t stream) {
+template <bool FP32, int W>
+static hipError_t launch_lrn_w(const LoopArgs &a, size_t lds, hipStream_t stream) {
   const GroupLayout L = make_layout(a.nv_max, 64, FP32 ? 1 : 0, 0, a.grid_words);
-  auto kern = L.nlev_max <= 2 ? k_event_loop<64, 1, FP32, false, 2, true>
-                              : k_event_loop<64, 1, FP32, false, 3, true>;
+  auto kern = L.nlev_max <= 2 ? k_event_loop<64, W, FP32, false, 2, true>
+                              : k_event_loop<64, W, FP32, false, 3, true>;
   hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds);
   if (e != hipSuccess) return e;
-  // with both networks a second wavefront evaluates the Poisson network
-  const int threads = a.pol_blob && a.pt_blob ? 128 : 64;
-  hipLaunchKernelGGL(kern, dim3(1), dim3(threads), lds, stream, a, L);
+  hipLaunchKernelGGL(kern, dim3(1), dim3(64 * W), lds, stream, a, L);
   return hipGetLastError();
+}
+
+template <bool FP32>
+static hipError_t launch_lrn(const LoopArgs &a, size_t lds, hipStream_t stream) {
+  // with both networks a second wavefront evaluates the Poisson network
+  return a.pol_blob && a.pt_blob ? launch_lrn_w<FP32, 2>(a, lds, stream) : launch_lrn_w<FP32, 1>(a, lds, stream);
 }
 
 hipError_t launch_event_loop_lrn(const LoopArgs &a, int precision, int refresh_full, size_t lds,
