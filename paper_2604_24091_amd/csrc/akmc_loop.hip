@@ -1423,7 +1423,7 @@ struct Runner {
       dig = digest_event(dig, si, sj);
       n += 1;
 
-      if (!MLP && na == 1) {
+      if (na == 1) {
         // Only the moved vacancy: its box is already gathered.
 #pragma unroll
         for (int m = 0; m < M0; ++m) {
@@ -1438,7 +1438,11 @@ struct Runner {
         gsync();
         const int kk = gl & 7;
         double r = 0.0;
-        if (gl < 8) {
+        if (MLP) {
+          // the surrogate on this machine: a pass of one slot (aff[0] is v)
+          int vq = v;
+          r = eval_mlp_pass(1, gl >> 3, kk, 0, vq);
+        } else if (gl < 8) {
           int Ak;
           Real ea;
           if (FAR && G < 64)
@@ -1450,7 +1454,7 @@ struct Runner {
             if (eat) eat[v * 8 + kk] = ea;
           }
         }
-        if constexpr (FAR && G == 64) {
+        if constexpr (FAR && G == 64 && !MLP) {
           // six shells: all 64 lanes count, 8 per candidate
           int Ak;
           Real ea;
