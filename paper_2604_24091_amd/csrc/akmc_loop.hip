@@ -447,15 +447,16 @@ __device__ inline void mlp_tile_waves(const MlpLds &ml, int k1, int w, float *yo
   static_assert(kCpw * kMlpWaves == kHid / 16, "whole hidden-unit tiles per wavefront");
   const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
   const int ld1 = mlp_ld1(k1), nk = k1 / 32;
+  // The first product of each layer takes a zero accumulator operand;
+  // activations are converted to bfloat16 two at a time.
   f32x4 acc[kCpw];
-#pragma unroll
-  for (int cc = 0; cc < kCpw; ++cc) acc[cc] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int t = 0; t < nk; ++t) {
     const bf16x8 a = *(const bf16x8 *)(ml.atile + r * ld1 + 32 * t + 8 * q);
 #pragma unroll
     for (int cc = 0; cc < kCpw; ++cc) {
       const bf16x8 b = *(const bf16x8 *)(ml.w1t + (16 * (kCpw * w + cc) + r) * ld1 + 32 * t + 8 * q);
-      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cc], 0, 0, 0);
+      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          a, b, t == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[cc], 0, 0, 0);
     }
   }
 #pragma unroll
@@ -463,18 +464,21 @@ __device__ inline void mlp_tile_waves(const MlpLds &ml, int k1, int w, float *yo
     const int c = kCpw * w + cc;
     const float bias = ml.pb[16 * c + r];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) ml.hst[(4 * q + i) * kLdH + 16 * c + r] = f2bf(gelu_f(acc[cc][i] + bias));
+    for (int i = 0; i < 4; i += 2) {
+      const uint32_t hp = f2bf2(gelu_f(acc[cc][i] + bias), gelu_f(acc[cc][i + 1] + bias));
+      ml.hst[(4 * q + i) * kLdH + 16 * c + r] = (unsigned short)hp;
+      ml.hst[(4 * q + i + 1) * kLdH + 16 * c + r] = (unsigned short)(hp >> 16);
+    }
   }
   __syncthreads();
-#pragma unroll
-  for (int cc = 0; cc < kCpw; ++cc) acc[cc] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const bf16x8 a = *(const bf16x8 *)(ml.hst + r * kLdH + 32 * t + 8 * q);
 #pragma unroll
     for (int cc = 0; cc < kCpw; ++cc) {
       const bf16x8 b = *(const bf16x8 *)(ml.w2t + (16 * (kCpw * w + cc) + r) * kLdH + 32 * t + 8 * q);
-      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cc], 0, 0, 0);
+      acc[cc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          a, b, t == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[cc], 0, 0, 0);
     }
   }
   unsigned short *h2 = ml.atile;  // every wavefront has read its inputs (barrier above)
@@ -483,7 +487,11 @@ __device__ inline void mlp_tile_waves(const MlpLds &ml, int k1, int w, float *yo
     const int c = kCpw * w + cc;
     const float bias = ml.pb[kHid + 16 * c + r];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) h2[(4 * q + i) * kLdH + 16 * c + r] = f2bf(gelu_f(acc[cc][i] + bias));
+    for (int i = 0; i < 4; i += 2) {
+      const uint32_t hp = f2bf2(gelu_f(acc[cc][i] + bias), gelu_f(acc[cc][i + 1] + bias));
+      h2[(4 * q + i) * kLdH + 16 * c + r] = (unsigned short)hp;
+      h2[(4 * q + i + 1) * kLdH + 16 * c + r] = (unsigned short)(hp >> 16);
+    }
   }
   __syncthreads();
   constexpr int kIpw = 4 / kMlpWaves;  // output rows per lane and wavefront

@@ -87,6 +87,12 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
   // round to nearest even: the hardware conversion (v_cvt_pk_bf16_f32)
   return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
+// Two values to bfloat16 with one conversion; the first in the low half.
+__device__ __forceinline__ uint32_t f2bf2(float a, float b) {
+  typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+  typedef float f32x2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){a, b}, bf16x2));
+}
 __device__ __forceinline__ float bf2f(unsigned short h) {
   return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
@@ -95,11 +101,13 @@ __device__ __forceinline__ float bf2f(unsigned short h) {
 //   gelu(z) = z/2 (1 + tanh u) = z s,  s = 1 / (1 + e^{-2u}),
 //   u = sqrt(2/pi) (z + 0.044715 z^3),
 // with one hardware base-2 exponential and one reciprocal (about 1e-7
-// relative, far below the bfloat16 rounding of the activations).
+// relative, far below the bfloat16 rounding of the activations).  The
+// exponent -2u log2(e) is formed as z (b + a z^2), b = -2 sqrt(2/pi) log2(e),
+// a = 0.044715 b.
 __device__ __forceinline__ float gelu_sig(float z) {
-  const float k = 2.0f * 0.7978845608028654f * 1.4426950408889634f;  // 2 sqrt(2/pi) log2(e)
-  const float t = z * fmaf(0.044715f * z, z, 1.0f);
-  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-k * t));
+  const float b = -(2.0f * 0.7978845608028654f * 1.4426950408889634f);
+  const float a = 0.044715f * b;
+  return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * fmaf(a * z, z, b)));
 }
 __device__ __forceinline__ float gelu_f(float z) { return z * gelu_sig(z); }
 // d/dz [z s] = s + z s (1 - s) 2u'(z),  u' = sqrt(2/pi) (1 + 3 * 0.044715 z^2)
@@ -209,9 +217,8 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
   const int l = threadIdx.x & 63;
   const int r = l & 15, q = l >> 4;
   // Layer 1: A from the one-hot codes (row r, features 32t + 8q .. +7).
+  // The first product of every tile takes a zero accumulator operand.
   f32x4 acc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int nk = k1 / 32;
   const int mg = s_magic(S);
   for (int t = 0; t < nk; ++t) {
@@ -230,19 +237,25 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const bf16x8 b = *(const bf16x8 *)(w1t + (16 * c + r) * mlp_ld1(k1) + 32 * t + 8 * q);
-      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          a, b, t == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[c], 0, 0, 0);
     }
   }
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const float bias = prm[L.ob1 + 16 * c + r];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float z = acc[c][i] + bias;
-      const unsigned short hb = f2bf(gelu_f(z));
-      h1b[c][i] = hb;
-      if (GRAD) gp1[c][i] = gelu_grad_f(z);
-      hst[(4 * q + i) * kLdH + 16 * c + r] = hb;
+    for (int i = 0; i < 4; i += 2) {
+      const float z0 = acc[c][i] + bias, z1 = acc[c][i + 1] + bias;
+      const uint32_t hp = f2bf2(gelu_f(z0), gelu_f(z1));
+      h1b[c][i] = (unsigned short)hp;
+      h1b[c][i + 1] = (unsigned short)(hp >> 16);
+      if (GRAD) {
+        gp1[c][i] = gelu_grad_f(z0);
+        gp1[c][i + 1] = gelu_grad_f(z1);
+      }
+      hst[(4 * q + i) * kLdH + 16 * c + r] = (unsigned short)hp;
+      hst[(4 * q + i + 1) * kLdH + 16 * c + r] = (unsigned short)(hp >> 16);
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -250,14 +263,13 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // Layer 2: A = h1 rows from the staging tile.
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
   for (int t = 0; t < 4; ++t) {
     const bf16x8 a = *(const bf16x8 *)(hst + r * kLdH + 32 * t + 8 * q);
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const bf16x8 b = *(const bf16x8 *)(w2t + (16 * c + r) * kLdH + 32 * t + 8 * q);
-      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[c], 0, 0, 0);
+      acc[c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          a, b, t == 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : acc[c], 0, 0, 0);
     }
   }
   float part[4] = {0.f, 0.f, 0.f, 0.f};
@@ -266,12 +278,17 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
     const float bias = prm[L.ob2 + 16 * c + r];
     const float w3 = bf2f(f2bf(prm[L.ow3 + 16 * c + r]));
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float z = acc[c][i] + bias;
-      const unsigned short hb = f2bf(gelu_f(z));
-      h2b[c][i] = hb;
-      if (GRAD) gp2[c][i] = gelu_grad_f(z);
-      part[i] = fmaf(bf2f(hb), w3, part[i]);
+    for (int i = 0; i < 4; i += 2) {
+      const float z0 = acc[c][i] + bias, z1 = acc[c][i + 1] + bias;
+      const uint32_t hp = f2bf2(gelu_f(z0), gelu_f(z1));
+      h2b[c][i] = (unsigned short)hp;
+      h2b[c][i + 1] = (unsigned short)(hp >> 16);
+      if (GRAD) {
+        gp2[c][i] = gelu_grad_f(z0);
+        gp2[c][i + 1] = gelu_grad_f(z1);
+      }
+      part[i] = fmaf(__builtin_bit_cast(float, hp << 16), w3, part[i]);
+      part[i + 1] = fmaf(__builtin_bit_cast(float, hp & 0xffff0000u), w3, part[i + 1]);
     }
   }
   // Sum the 16 lanes of each row group (lanes 16q .. 16q+15).
