@@ -447,6 +447,7 @@ __device__ inline void mlp_tile_waves(const MlpLds &ml, int k1, int w, float *yo
   static_assert(kCpw * kMlpWaves == kHid / 16, "whole hidden-unit tiles per wavefront");
   const int l = threadIdx.x & 63, r = l & 15, q = l >> 4;
   const int ld1 = mlp_ld1(k1), nk = k1 / 32;
+  __builtin_assume(nk >= 1);  // k1 = 32 * ceil(27 S / 32) with S >= 2
   // The first product of each layer takes a zero accumulator operand;
   // activations are converted to bfloat16 two at a time.
   f32x4 acc[kCpw];

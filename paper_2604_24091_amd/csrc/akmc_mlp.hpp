@@ -186,10 +186,27 @@ __device__ __forceinline__ void onehot_tile_rows(const uint8_t *env, int64_t row
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int rows = n - row0 < 16 ? (int)(n - row0) : 16;
   const uint8_t *src = env + row0 * kSlots;  // rows are contiguous: element u = row * kSlots + slot
-  for (int u = lane; u < rows * kSlots; u += 64) {
-    const int row = u / kSlots, slot = u - row * kSlots;
-    const int code = src[u];
-    if (code < S) atile[row * ld + slot * S + code] = 0x3F80;  // bf16 1.0
+  // Element u = lane + 64 j: every code is loaded before the first store,
+  // and the tile offset row * ld + slot * S advances by 64 elements per j
+  // (64 = 2 kSlots + 10, so slot wraps at most once per step).
+  constexpr int kJ = (16 * kSlots + 63) / 64;
+  static_assert(64 - 2 * kSlots >= 0 && 64 - 2 * kSlots < kSlots, "one wrap per step");
+  const int nu = rows * kSlots;
+  int code[kJ];
+#pragma unroll
+  for (int j = 0; j < kJ; ++j) code[j] = lane + 64 * j < nu ? src[lane + 64 * j] : S;
+  int slot = lane % kSlots;
+  int d = (lane / kSlots) * ld + slot * S;
+  const int step = 2 * ld + (64 - 2 * kSlots) * S, wrap = ld - kSlots * S;
+#pragma unroll
+  for (int j = 0; j < kJ; ++j) {
+    if (code[j] < S) atile[d + code[j]] = 0x3F80;  // bf16 1.0
+    slot += 64 - 2 * kSlots;
+    d += step;
+    if (slot >= kSlots) {
+      slot -= kSlots;
+      d += wrap;
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -220,6 +237,7 @@ __device__ __forceinline__ void mlp_fwd16(const uint8_t *env, const unsigned sho
   // The first product of every tile takes a zero accumulator operand.
   f32x4 acc[8];
   const int nk = k1 / 32;
+  __builtin_assume(nk >= 1);  // k1 = 32 * ceil(27 S / 32) with S >= 2
   const int mg = s_magic(S);
   for (int t = 0; t < nk; ++t) {
     bf16x8 a;
