@@ -165,10 +165,38 @@ __device__ __forceinline__ void onehot_tile(const uint8_t *codes, unsigned short
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (int u = lane; u < 16 * kSlots; u += 64) {
-    const int row = u / kSlots, slot = u - row * kSlots;
-    const int code = codes[row * 32 + slot];
-    if (code < S) atile[row * ld + slot * S + code] = 0x3F80;  // bf16 1.0
+  // Element u = lane + 64 j (row u / kSlots, slot u % kSlots): every code is
+  // read before the first store; the source and tile offsets advance by 64
+  // elements per j (64 = 2 kSlots + 10, so slot wraps at most once a step).
+  constexpr int kJ = (16 * kSlots + 63) / 64;
+  constexpr int kStep = 64 - 2 * kSlots;
+  static_assert(kStep >= 0 && kStep < kSlots, "one wrap per step");
+  int code[kJ];
+  {
+    int slot = lane % kSlots, src = (lane / kSlots) * 32 + slot;
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+      code[j] = lane + 64 * j < 16 * kSlots ? codes[src] : S;
+      slot += kStep;
+      src += 2 * 32 + kStep;
+      if (slot >= kSlots) {
+        slot -= kSlots;
+        src += 32 - kSlots;
+      }
+    }
+  }
+  int slot = lane % kSlots;
+  int d = (lane / kSlots) * ld + slot * S;
+  const int step = 2 * ld + kStep * S, wrap = ld - kSlots * S;
+#pragma unroll
+  for (int j = 0; j < kJ; ++j) {
+    if (code[j] < S) atile[d + code[j]] = 0x3F80;  // bf16 1.0
+    slot += kStep;
+    d += step;
+    if (slot >= kSlots) {
+      slot -= kSlots;
+      d += wrap;
+    }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
