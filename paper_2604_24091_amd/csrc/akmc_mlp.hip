@@ -271,9 +271,18 @@ __global__ __launch_bounds__(64 * kTrainTileWaves) void k_mlp_train_partial(Trai
   constexpr int kMaxT1 = mlp_k1(8) / 32;
   const int nk = k1 / 32;
   bf16x8 bw1[kMaxT1], bw2[4], bw2r[4];
+  // Every chunk is loaded without a branch, so all are in flight together;
+  // chunks past k1 read the last one again and are never used.
 #pragma unroll
   for (int t = 0; t < kMaxT1; ++t)
-    if (t < nk) bw1[t] = *(const bf16x8 *)(gw1t + col * k1 + 32 * t + 8 * q);
+    bw1[t] = *(const bf16x8 *)(gw1t + col * k1 + 32 * (t < nk ? t : nk - 1) + 8 * q);
+  // The binary32 parameters this lane uses, read here rather than after the
+  // barriers below (a read there would wait a full memory round trip).
+  const float b1c = prm[L.ob1 + col], b2c = prm[L.ob2 + col], b3 = prm[L.ob3];
+  const float w3c = bf2f(f2bf(prm[L.ow3 + col]));
+  float w3r[kTrainTileWaves];
+#pragma unroll
+  for (int c = 0; c < kTrainTileWaves; ++c) w3r[c] = bf2f(f2bf(prm[L.ow3 + 16 * c + r]));
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     bw2[t] = *(const bf16x8 *)(gw2t + col * kHid + 32 * t + 8 * q);
@@ -295,11 +304,13 @@ __global__ __launch_bounds__(64 * kTrainTileWaves) void k_mlp_train_partial(Trai
       const int64_t pos = ta.start + b;
       drow = ta.perm_key ? permute_row(pos, ta.n, ta.perm_key, ta.perm_bits) : pos;
     }
+    // the row's target is read beside its codes, not after them
+    const float eav = uslot == 0 && drow >= 0 ? ta.ea[drow] : 0.f;
     ucode = drow >= 0 ? ta.env[drow * kSlots + uslot] : 0;
     senv[urow * 32 + uslot] = (uint8_t)ucode;
     if (uslot == 0) {
       const bool valid = drow >= 0 && ucode != S - 1;
-      s_t[urow] = valid ? (ta.ea[drow] - mu) / sigma : 0.f;
+      s_t[urow] = valid ? (eav - mu) / sigma : 0.f;
       s_valid[urow] = valid ? 1 : 0;
     }
   }
@@ -318,7 +329,7 @@ __global__ __launch_bounds__(64 * kTrainTileWaves) void k_mlp_train_partial(Trai
   }
   float gp1[4], gp2[4];
   {
-    const float bias = prm[L.ob1 + col];
+    const float bias = b1c;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const float z = acc[i] + bias;
@@ -337,7 +348,7 @@ __global__ __launch_bounds__(64 * kTrainTileWaves) void k_mlp_train_partial(Trai
   }
   unsigned short h2b[4];
   {
-    const float bias = prm[L.ob2 + col];
+    const float bias = b2c;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const float z = acc[i] + bias;
@@ -355,7 +366,7 @@ __global__ __launch_bounds__(64 * kTrainTileWaves) void k_mlp_train_partial(Trai
     float part[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < kTrainTileWaves; ++c) {
-      const float w3 = bf2f(f2bf(prm[L.ow3 + 16 * c + r]));
+      const float w3 = w3r[c];
 #pragma unroll
       for (int i = 0; i < 4; ++i) part[i] = fmaf(bf2f(h2s[(4 * q + i) * kLdH + 16 * c + r]), w3, part[i]);
     }
@@ -366,7 +377,7 @@ __global__ __launch_bounds__(64 * kTrainTileWaves) void k_mlp_train_partial(Trai
       v += __shfl_xor(v, 4, 16);
       v += __shfl_xor(v, 2, 16);
       v += __shfl_xor(v, 1, 16);
-      y[i] = v + prm[L.ob3];
+      y[i] = v + b3;
     }
   }
 
@@ -395,7 +406,7 @@ __global__ __launch_bounds__(64 * kTrainTileWaves) void k_mlp_train_partial(Trai
   // Output-layer gradients of this tile.
   s16x4 dz2b;
   {
-    const float w3 = bf2f(f2bf(prm[L.ow3 + col]));
+    const float w3 = w3c;
     float dw3 = 0.f, db2 = 0.f;
     float dz2[4];
 #pragma unroll
