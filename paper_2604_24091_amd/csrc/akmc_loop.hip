@@ -748,27 +748,39 @@ struct Runner {
       vv = s.aff[p0 + q];
       const int flip = (~k) & 7;
       const int jb = kBoxC + dir_sx(k) + 7 * dir_sy(k) + 49 * dir_sz(k);
+      // Every box byte is read before the first row byte is written (the
+      // compiler cannot tell the row from the box, so a write between two
+      // reads would make the second wait for the first).
+      uint8_t n1i[8], n1j[8], n2i[6], n2j[6];
       A = box[jb] >> 2;
-      row[0] = (uint8_t)A;
-      uint32_t c1i = 0, c1j = 0, c2i = 0, c2j = 0;
 #pragma unroll
       for (int d2 = 0; d2 < 8; ++d2) {
         const int qq = d2 ^ flip;
         const int off = dir_sx(qq) + 7 * dir_sy(qq) + 49 * dir_sz(qq);
-        const uint8_t si = box[kBoxC + off] >> 2, sj = box[jb + off] >> 2;
-        if (d2 < 7) { row[1 + d2] = si; c1i += onehot(si); }
-        if (d2 > 0) { row[13 + d2] = sj; c1j += onehot(sj); }
+        n1i[d2] = box[kBoxC + off] >> 2;
+        n1j[d2] = box[jb + off] >> 2;
       }
 #pragma unroll
       for (int m = 0; m < 6; ++m) {
         const int axis = m >> 1;
         const int mm = ((flip >> (2 - axis)) & 1) ? (m ^ 1) : m;
         const int off = ((mm & 1) ? -1 : 1) * (axis == 0 ? 2 : axis == 1 ? 14 : 98);
-        const uint8_t si = box[kBoxC + off] >> 2, sj = box[jb + off] >> 2;
-        row[8 + m] = si;
-        row[21 + m] = sj;
-        c2i += onehot(si);
-        c2j += onehot(sj);
+        n2i[m] = box[kBoxC + off] >> 2;
+        n2j[m] = box[jb + off] >> 2;
+      }
+      row[0] = (uint8_t)A;
+      uint32_t c1i = 0, c1j = 0, c2i = 0, c2j = 0;
+#pragma unroll
+      for (int d2 = 0; d2 < 8; ++d2) {
+        if (d2 < 7) { row[1 + d2] = n1i[d2]; c1i += onehot(n1i[d2]); }
+        if (d2 > 0) { row[13 + d2] = n1j[d2]; c1j += onehot(n1j[d2]); }
+      }
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        row[8 + m] = n2i[m];
+        row[21 + m] = n2j[m];
+        c2i += onehot(n2i[m]);
+        c2j += onehot(n2j[m]);
       }
       if (A != V) {
         // N1(i) without j does not contain the moving atom's site; the box
